@@ -1,0 +1,61 @@
+"""The oracle's pins must catch plausible mistakes: each case plants one in the
+oracle (CPU only, via monkeypatch) and checks that a pin test then fails."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import zf_oracle as O
+from tests import test_oracle_coeffs as TC
+from tests import test_oracle_recursion as TR
+from tests import test_oracle_split as TS
+
+
+def _dropped_term(m):
+    c = [Fraction(1), Fraction(1, 2), Fraction(3, 8), Fraction(5, 16), Fraction(35, 128),
+         Fraction(63, 256)][: m + 1]
+    if m >= 2:
+        c[2] = Fraction(1, 4)
+    return c
+
+
+def _flipped_correction(delta, order):
+    c = [float(x) for x in O.delta_coefficients(order)]
+    q = c[1] * delta + (c[2] * delta @ delta if order >= 2 else 0.0)
+    return -q
+
+
+def _transposed_gram(S, Z):
+    return Z @ S @ Z.T
+
+
+def _truncating_split(a, fmt="bf16"):
+    a32 = O.to_fp32(a)
+    u = np.ascontiguousarray(a32).view(np.uint32) & np.uint32(0xFFFF0000)
+    hi = u.view(np.float32)
+    r = (a32 - hi).astype(np.float32)
+    lo = (np.ascontiguousarray(r).view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32)
+    return hi, lo
+
+
+def _nonstrict_stop(it, err, prev, order, rule):
+    if it == 0 or prev is None:
+        return False
+    return err >= prev ** (order + 1)
+
+
+MUTANTS = [
+    ("delta_coefficients", _dropped_term, lambda g: TR.test_spectral_map_history()),
+    ("delta_coefficients", _dropped_term, lambda g: TC.test_x_form_coefficients_match_appendix_a(g)),
+    ("correction", _flipped_correction, lambda g: TR.test_spectral_map_history()),
+    ("gram", _transposed_gram, lambda g: TR.test_general_guess_limit()),
+    ("split", _truncating_split, lambda g: TS.test_bf16_rounding_edge_values()),
+    ("stop_now", _nonstrict_stop, lambda g: TC.test_stop_rule_algorithm_2()),
+]
+
+
+@pytest.mark.parametrize("name,mutant,pin", MUTANTS, ids=[f"{m[0]}-{i}" for i, m in enumerate(MUTANTS)])
+def test_pin_catches_mutant(monkeypatch, golden_dir, name, mutant, pin):
+    monkeypatch.setattr(O, name, mutant)
+    with pytest.raises(AssertionError):
+        pin(golden_dir)
