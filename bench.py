@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the refinement hot path on one MI355X.
+
+One step = one complete zf_refine call on one synthetic overlap matrix: setup
+(split, Z0), every low-precision sweep, the FP64 refinement phase with its
+residual evaluations, and the copy-out of Z.  Inputs are resident in HBM before
+the timed region starts.
+
+Reported (one JSON line):
+  value        refined-Z TFLOP/s of the mixed path (BF16x3 sweeps + FP64
+               refinement): algorithmic flops / time, where one residual
+               evaluation counts 4 N^3 (S Z and Z^T (S Z)) and one update of
+               order m counts 2 m N^3 (delta^k products and Z Q)
+  ms_per_step  its time-to-solution; fp64.* holds the plain FP64 path
+  roofline     the dominant kernel (most time in the timed region), timed with
+               HIP events on the library's stream
+  cpu_baseline the CPU FP64 oracle on a bounded sample of the same workload
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("refined-Z TFLOP/s + time-to-‖ZᵀSZ−I‖≤1e-6, mixed vs FP64 path, "
+          "1 MI355X")
+PEAK_TFLOPS = {"bf16": 2500.0, "fp64": 78.6}
+KCLASS_DTYPE = {"gemm_x3": "bf16", "gemm_x3_sym": "bf16", "gemm_f64": "fp64", "gemm_f64_sym": "fp64"}
+
+WORKLOADS = {
+    "gauss4096": dict(n=4096, sigma=1.0,
+                      desc="Gaussian-kernel overlap, N=4096 atoms at 0.1/A^3 (random sequential "
+                           "addition, d_min 0.8 A), S_ij=exp(-r^2/2), sigma 1.0 A"),
+    "gauss256": dict(n=256, sigma=1.2,
+                     desc="Gaussian-kernel overlap, N=256, sigma 1.2 A"),
+    "cluster5049": dict(n=5049, sigma=None,
+                        desc="561-atom fcc cuboctahedron, 1s+3p+5d Gaussians, alpha 0.08 bohr^-2, "
+                             "N=5049"),
+}
+
+
+def alg_flops(n: int, order: int, evals: int, updates: int) -> float:
+    return float(n) ** 3 * (4.0 * evals + 2.0 * order * updates)
+
+
+def kernel_alg_flops(cls: str, n: int) -> float:
+    """Algorithmic flops of one launch at order n (no padding, no duplicated work)."""
+    n = float(n)
+    return {"gemm_x3": 6 * n ** 3, "gemm_x3_sym": 3 * n * n * (n + 1),
+            "gemm_f64": 2 * n ** 3, "gemm_f64_sym": n * n * (n + 1)}[cls]
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="gauss4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--order", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed-only", action="store_true", help="skip the FP64 path (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the refinement of one matrix runs on one device and "
+              "this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2404_19163_amd import inputs, zf
+
+    wl = WORKLOADS[args.workload]
+    n = wl["n"]
+    t0 = time.perf_counter()
+    S_np = inputs.workload(args.workload, args.seed)
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] generated {args.workload} N={n} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    S = torch.from_numpy(S_np).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def run(precision, out):
+        return zf.refine(S, None, order=args.order, precision=precision, out=out, stream=stream,
+                         refine="f64_delta")
+
+    # ---- mixed path (the headline) --------------------------------------
+    Zm = torch.empty_like(S)
+    for _ in range(args.warmup):
+        run("bf16x3", Zm)
+    torch.cuda.synchronize()
+    zf.profile_reset()
+    zf.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(args.steps):
+        last = run("bf16x3", Zm)
+    torch.cuda.synchronize()
+    mixed_s = (time.perf_counter() - t0) / args.steps
+    zf.profile_enable(False)
+    prof = zf.profile_read()
+    print(f"[bench] mixed: {mixed_s * 1e3:.3f} ms/step iters={last.iters} "
+          f"evals={last.low_evals}+{last.high_evals} rms={last.final_rms:.3e}", file=sys.stderr,
+          flush=True)
+
+    mixed_flops = alg_flops(n, args.order, last.low_evals + last.high_evals,
+                            (last.low_evals - 1) + max(last.high_evals - 1, 0))
+    value = mixed_flops / mixed_s / 1e12
+
+    # dominant kernel of the timed region
+    dom = max(prof, key=lambda k: prof[k][1])
+    launches, tot_ms, exec_flops = prof[dom]
+    avg_s = tot_ms / 1e3 / max(launches, 1)
+    ach = kernel_alg_flops(dom, n) / avg_s / 1e12
+    peak = PEAK_TFLOPS[KCLASS_DTYPE[dom]]
+    kernels = {k: {"launches": v[0], "total_ms": round(v[1], 4),
+                   "avg_us": round(v[1] / max(v[0], 1) * 1e3, 2),
+                   "share": round(v[1] / max(mixed_s * 1e3 * args.steps, 1e-9), 4),
+                   "alg_tflops": round(kernel_alg_flops(k, n) / (v[1] / 1e3 / v[0]) / 1e12, 2)
+                   if v[0] else None}
+               for k, v in prof.items()}
+
+    # ---- FP64 path -------------------------------------------------------
+    fp64 = None
+    if not args.mixed_only and args.fp64_steps > 0:
+        Zd = torch.empty_like(S)
+        run("fp64", Zd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r64 = None
+        for _ in range(args.fp64_steps):
+            r64 = run("fp64", Zd)
+        torch.cuda.synchronize()
+        fp64_s = (time.perf_counter() - t0) / args.fp64_steps
+        f64_flops = alg_flops(n, args.order, r64.high_evals, r64.high_evals - 1)
+        fp64 = {"ms": round(fp64_s * 1e3, 3), "tflops": round(f64_flops / fp64_s / 1e12, 3),
+                "iters": r64.iters, "final_rms": r64.final_rms}
+        print(f"[bench] fp64: {fp64_s * 1e3:.3f} ms/step iters={r64.iters} rms={r64.final_rms:.3e}",
+              file=sys.stderr, flush=True)
+
+    # ---- residuals checked by the CPU oracle ----------------------------
+    from oracle import zf_oracle as O
+    Zm_np = Zm.cpu().numpy()
+    oracle_rms_mixed = O.residual_rms(S_np, Zm_np)
+    checks = {"oracle_rms_mixed": oracle_rms_mixed}
+    if fp64 is not None:
+        Zd_np = Zd.cpu().numpy()
+        checks["oracle_rms_fp64"] = O.residual_rms(S_np, Zd_np)
+        checks["rel_diff_mixed_vs_fp64"] = float(np.linalg.norm(Zm_np - Zd_np) / np.linalg.norm(Zd_np))
+
+    # ---- CPU baseline: the oracle on a bounded sample --------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        Z0 = O.scaled_identity_guess(S_np)
+        t0 = time.perf_counter()
+        res = O.refine(S_np, Z0, order=args.order, rule="none", max_sweeps=1)
+        cpu_s = time.perf_counter() - t0
+        cf = alg_flops(n, args.order, len(res.hist), len(res.hist) - 1)
+        cores = len(os.sched_getaffinity(0))
+        cpu = {"value": round(cf / cpu_s / 1e12, 5), "unit": "TFLOP/s", "cores": cores,
+               "threads": torch.get_num_threads(), "kind": "oracle",
+               "sample": f"{args.workload}: 2 FP64 residual evaluations + 1 update of the oracle "
+                         f"recursion ({cf:.3e} alg. flops) in {cpu_s:.2f} s"}
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed_s * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3+fp64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": n, "seed": args.seed, "order": args.order,
+                   "z0": "scaled identity", "stop": "ratio (Algorithm 2)",
+                   "refine": "FP64 residual + BF16x3 correction"},
+        "time_to_solution_ms": round(mixed_s * 1e3, 4),
+        "iters": last.iters,
+        "low_evals": last.low_evals,
+        "high_evals": last.high_evals,
+        "final_rms": last.final_rms,
+        "fp64": fp64,
+        "speedup_vs_fp64": round(fp64["ms"] / (mixed_s * 1e3), 3) if fp64 else None,
+        "checks": checks,
+        "kernels": kernels,
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(ach, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,183 @@
+/*
+ * zf.h -- C ABI of libzf: iterative refinement of an inverse overlap factor Z
+ * with Z^T S Z = I (equivalently Z Z^T = S^-1) for a dense symmetric
+ * positive-definite overlap matrix S, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Habib, Finkelstein & Niklasson, "Efficient Mixed-Precision Matrix
+ * Factorization of the Inverse Overlap Matrix in Electronic Structure
+ * Calculations with AI-Hardware and GPUs" (LA-UR-24-24032):
+ *   - recursion Z_{n+1} = Z_n sum_k c_k delta_n^k with delta_n = I - Z_n^T S Z_n
+ *     (Sec. III, Eq. np1 and its delta form), c_k = C(2k,k)/4^k;
+ *   - parameter-free stop test (Sec. IV.A, Algorithm 2, Eq. stopL2);
+ *   - two-term split A = A^(h) + A^(l) with the (h)(h)+(h)(l)+(l)(h) products
+ *     (Sec. III.A-B, Eqs. dualRep, splitStyle, SZn, Xn, Xsq);
+ *   - a refinement phase in higher precision after the low-precision stop
+ *     (Sec. IV.B, Algorithm 3).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are dense, row-major, leading dimension n, FP64, in DEVICE
+ *     memory (hipMalloc'd or a torch CUDA tensor).  S must be symmetric; only
+ *     its values are read, never written.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *     stream).  Work is ordered on that stream.  Calls that report scalars to
+ *     the host (iteration counts, histories, norms) synchronize the stream
+ *     before returning.
+ *   - Ownership: the caller owns every pointer it passes.  The library owns a
+ *     per-device workspace cache sized for the largest n seen, allocated on
+ *     first use and freed by zf_release().
+ *   - Return value: 0 on success; a positive value is a bitmask of ZF_WARN_*;
+ *     a negative value is a ZF_ERR_* code and zf_last_error() describes it.
+ *     Nothing throws or aborts across this ABI.
+ *   - Calls are not reentrant: do not run two calls concurrently from
+ *     different host threads on one device.
+ */
+#ifndef ZF_H
+#define ZF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ZF_OK 0
+/* warnings (bitmask, positive) */
+#define ZF_WARN_MAXSWEEPS 1   /* a phase ended at its sweep cap, not at the stop test */
+#define ZF_WARN_HIST_TRUNC 4  /* more residuals than hist_cap; the rest were dropped */
+/* errors (negative) */
+#define ZF_ERR_ARG -1            /* invalid argument (n <= 0, order out of range, NULL, ...) */
+#define ZF_ERR_NOMEM -2          /* device or pinned allocation failed */
+#define ZF_ERR_HIP -3            /* a HIP runtime call failed (message has hipGetErrorString) */
+#define ZF_ERR_NONFINITE -4      /* a residual norm was NaN or Inf (S or Z0 not finite, or overflow) */
+#define ZF_ERR_NOT_CONVERGED -5  /* returned Z has ||Z^T S Z - I||_F >= 1: the convergence
+                                    condition ||X0 - I||_2 < 1 of Sec. III was not met */
+
+/* Arithmetic of the low-precision phase (Sec. III, Table I). */
+enum zf_precision {
+  ZF_FP64 = 0,    /* "double": every product in FP64 on the FP64 matrix cores      */
+  ZF_BF16X3 = 1,  /* (h)(h)+(h)(l)+(l)(h) with BF16 halves, FP32 accumulation       */
+  ZF_FP16X3 = 2   /* reserved for the FP16-halves variant; currently ZF_ERR_ARG      */
+};
+
+/* Stop rule (Sec. IV.A). */
+enum zf_stop {
+  ZF_STOP_RATIO = 0,    /* Algorithm 2: stop at n > 0 once Err_n > Err_{n-1}^(m+1)  */
+  ZF_STOP_MONOTONE = 1  /* stop at n > 0 once Err_n >= Err_{n-1}                    */
+};
+
+/* Refinement phase after a low-precision stop (Sec. IV.B, Algorithm 3). */
+enum zf_refine_mode {
+  ZF_REFINE_OFF = 0,       /* return the low-precision result                        */
+  ZF_REFINE_F64_DELTA = 1, /* FP64 delta and stop norm, low-precision correction      */
+  ZF_REFINE_F64_FULL = 2   /* FP64 delta and FP64 correction                         */
+};
+
+typedef struct {
+  int order;      /* m, number of series terms after I; 1..5 (the paper uses 2)          */
+  int precision;  /* enum zf_precision                                                   */
+  int stop;       /* enum zf_stop                                                        */
+  int max_sweeps; /* cap on Z updates in the first phase; <= 0 means 100                */
+  int refine;     /* enum zf_refine_mode; ignored for ZF_FP64                            */
+  int max_refine; /* cap on Z updates in the refinement phase; <= 0 means 10             */
+} zf_opts;
+
+typedef struct {
+  int iters;       /* Z updates contained in the returned Z (both phases)               */
+  int low_evals;   /* residual evaluations in the low-precision phase                   */
+  int high_evals;  /* FP64 residual evaluations (refinement phase or ZF_FP64 runs)     */
+  int hist_len;    /* entries written to hist                                           */
+  int flags;       /* ZF_WARN_* bits                                                    */
+  double final_err;/* ||I - Z^T S Z||_F of the returned Z as last evaluated (FP64 when a
+                      FP64 evaluation ran, else the low-precision value)               */
+  double final_rms;/* final_err / sqrt(n)                                              */
+} zf_result;
+
+/* Fill *opts with the defaults: order 2, ZF_BF16X3, ZF_STOP_RATIO, 100 sweeps,
+ * ZF_REFINE_F64_DELTA, 10 refinement sweeps. */
+void zf_default_opts(zf_opts* opts);
+
+/*
+ * zf_refine -- refine Z0 to Z with Z^T S Z = I (Sec. III-IV).
+ *   S     [in]  device, n x n FP64 symmetric positive definite.
+ *   Z0    [in]  device, n x n FP64 initial guess with ||Z0^T S Z0 - I||_2 < 1 (Sec. III),
+ *               or NULL for the scaled identity I / sqrt(max_i sum_j |S_ij|).
+ *   n     [in]  order of S, >= 1.
+ *   order [in]  m in 1..5.
+ *   precision [in] enum zf_precision; mixed precisions run ZF_REFINE_F64_DELTA.
+ *   Z     [out] device, n x n FP64; may alias Z0.
+ *   iters [out] host, Z updates in the returned Z (may be NULL).
+ *   hist  [out] host, hist_cap doubles: unnormalized ||delta||_F per residual
+ *               evaluation, first phase then refinement phase (may be NULL if
+ *               hist_cap is 0).
+ *   hist_len [out] host, entries written (may be NULL).
+ * Stop rule ZF_STOP_RATIO; see zf_refine_ex for every option.
+ */
+int zf_refine(const double* S, const double* Z0, int n, int order, int precision, double* Z,
+              int* iters, double* hist, int hist_cap, int* hist_len, void* stream);
+
+/* zf_refine_ex -- as zf_refine with explicit options (opts NULL = defaults) and a result
+ * record (res may be NULL). */
+int zf_refine_ex(const double* S, const double* Z0, int n, const zf_opts* opts, double* Z,
+                 zf_result* res, double* hist, int hist_cap, void* stream);
+
+/* zf_residual -- err_f = ||Z^T S Z - I||_F evaluated with FP64 products (host double).
+ * S, Z: device n x n FP64. */
+int zf_residual(const double* S, const double* Z, int n, double* err_f, void* stream);
+
+/* zf_release -- free every cached workspace of the current device. */
+void zf_release(void);
+
+/* zf_last_error -- message for the last nonzero return on this host thread ("" if none). */
+const char* zf_last_error(void);
+
+/* zf_version -- ABI version (increases when an entry point changes). */
+int zf_version(void);
+
+/*
+ * Per-kernel timing with HIP events recorded on the caller's stream around each
+ * matrix-core GEMM launch (for roofline accounting).  Kernel classes:
+ *   0 gemm_x3, 1 gemm_x3_sym, 2 gemm_f64, 3 gemm_f64_sym.
+ * zf_profile_enable(1) starts recording (events add a few microseconds per
+ * launch); totals accumulate until zf_profile_reset().  zf_profile_read fills
+ * the class name (static string), launch count, summed milliseconds and
+ * executed matrix-core flops (2 * tile^3 per tile step, three products per step
+ * for gemm_x3).  Returns ZF_ERR_ARG for an unknown class.
+ */
+void zf_profile_enable(int on);
+void zf_profile_reset(void);
+int zf_profile_read(int cls, const char** name, long long* launches, double* total_ms,
+                    double* flops);
+
+/*
+ * Kernel-level entry points, exported for unit tests.  They run one library
+ * kernel on caller data through padded internal buffers.
+ *
+ * zf_t_split -- two-term split of Sec. III.A (Eq. splitStyle): for each of the
+ *   count FP64 values a (device), x = FP32[a] (round to nearest even), hi = LP[x],
+ *   lo = LP[x - hi], LP = BF16 (fmt 1) or FP16 (fmt 2), round to nearest even.
+ *   hi, lo: device arrays of count raw 16-bit patterns.
+ */
+int zf_t_split(const double* a, int64_t count, uint16_t* hi, uint16_t* lo, int fmt,
+               void* stream);
+
+/*
+ * zf_t_gemm -- one GEMM with its epilogue:
+ *   C = alpha * D + beta * (A B^T) + gamma * I      (all device, FP64, row-major)
+ *   A: m x k (ld k), B: nn x k (ld k), D: m x nn (ld nn) or NULL, C: m x nn (ld nn).
+ *   precision ZF_FP64 runs the FP64 matrix-core kernel; ZF_BF16X3 splits A and B
+ *   (as zf_t_split) and runs the (h)(h)+(h)(l)+(l)(h) kernel with FP32 accumulation
+ *   (Sec. III.B).  sym != 0 requires m == nn, computes only tiles on or above the
+ *   diagonal and mirrors them (valid when A B^T is symmetric).
+ *   norm_sq (host, may be NULL) receives the sum of C_ij^2 in FP64.
+ */
+int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, const double* B,
+              double alpha, const double* D, double beta, double gamma, double* C,
+              double* norm_sq, void* stream);
+
+/* zf_t_gershgorin -- g = max_i sum_j |S_ij| (host double) for device S (n x n). */
+int zf_t_gershgorin(const double* S, int n, double* g, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZF_H */

@@ -1,0 +1,256 @@
+// Bandwidth-bound helpers of the refinement path (gfx950): operand preparation
+// (split, zero padding, layouts), the scaled-identity guess, the final copy-out
+// and the deterministic reduction of the per-tile norm partials.
+//
+// Every matrix kernel here is a grid-stride loop over 4 consecutive elements of
+// a row per thread, so reads and normal-layout writes are coalesced.
+#include "zf_internal.h"
+
+namespace zf {
+
+static inline int grid_for(size_t work, int block) {
+  size_t g = (work + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+// ---------------------------------------------------------------------------
+// S (n x n, ld_src) -> padded np x np: BF16 hi/lo pair (Sec. III.A: the FP64
+// value is first rounded to FP32, then split), optionally an FP64 / FP32 copy.
+// ---------------------------------------------------------------------------
+__global__ void split_pad_kernel(const double* __restrict__ src, int n, int ld_src, int np,
+                                 u16* __restrict__ hi, u16* __restrict__ lo,
+                                 double* __restrict__ c64, float* __restrict__ c32, int fmt) {
+  const size_t total = (size_t)np * np;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / np), j = (int)(e % np);
+    const double a = (i < n && j < n) ? src[(size_t)i * ld_src + j] : 0.0;
+    const float x = (float)a;
+    if (hi) {
+      u16 h, l;
+      if (fmt == 2) split_f16(x, h, l);
+      else split_bf16(x, h, l);
+      hi[e] = h;
+      lo[e] = l;
+    }
+    if (c64) c64[e] = a;
+    if (c32) c32[e] = x;
+  }
+}
+
+hipError_t launch_split_pad(const double* src, int n, int ld_src, int np, u16* hi, u16* lo,
+                            double* copy64, float* copy32, bool transpose_copy, int fmt,
+                            hipStream_t st) {
+  (void)transpose_copy;
+  const size_t total = (size_t)np * np;
+  hipLaunchKernelGGL(split_pad_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, src, n, ld_src,
+                     np, hi, lo, copy64, copy32, fmt);
+  return hipGetLastError();
+}
+
+__global__ void split_flat_kernel(const double* __restrict__ src, int64_t count, u16* __restrict__ hi,
+                                  u16* __restrict__ lo, int fmt) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const float x = (float)src[e];
+    u16 h, l;
+    if (fmt == 2) split_f16(x, h, l);
+    else split_bf16(x, h, l);
+    hi[e] = h;
+    lo[e] = l;
+  }
+}
+
+hipError_t launch_split_flat(const double* src, int64_t count, u16* hi, u16* lo, int fmt,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(split_flat_kernel, dim3(grid_for((size_t)count, 256)), dim3(256), 0, st, src,
+                     count, hi, lo, fmt);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gershgorin bound g = max_i sum_j |S_ij| (FP64).  One wave per row, then one
+// block takes the maximum.
+// ---------------------------------------------------------------------------
+__global__ void row_abs_kernel(const double* __restrict__ S, int n, int ld, double* __restrict__ rs) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= n) return;
+  const double* row = S + (size_t)wave * ld;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += fabs(row[j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) rs[wave] = s;
+}
+
+__global__ void max_kernel(const double* __restrict__ v, int n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, v[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+hipError_t launch_row_abs_max(const double* S, int n, int ld, double* row_sums, double* g_out,
+                              hipStream_t st) {
+  const int waves_per_block = 4;
+  hipLaunchKernelGGL(row_abs_kernel, dim3((n + waves_per_block - 1) / waves_per_block),
+                     dim3(64 * waves_per_block), 0, st, S, n, ld, row_sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, row_sums, n, g_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Z0 = I / sqrt(g) in every layout the sweep reads (g read on the device).
+// ---------------------------------------------------------------------------
+__global__ void init_identity_kernel(const double* __restrict__ g, int n, int np, float* z32,
+                                     double* z64r, double* z64c, u16* zr_hi, u16* zr_lo,
+                                     u16* zc_hi, u16* zc_lo) {
+  const double c = 1.0 / sqrt(g[0]);
+  const size_t total = (size_t)np * np;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / np), j = (int)(e % np);
+    const double v = (i == j && i < n) ? c : 0.0;
+    const float f = (float)v;
+    u16 h, l;
+    split_bf16(f, h, l);
+    if (z32) z32[e] = f;
+    if (z64r) z64r[e] = v;
+    if (z64c) z64c[e] = v;
+    if (zr_hi) { zr_hi[e] = h; zr_lo[e] = l; }
+    if (zc_hi) { zc_hi[e] = h; zc_lo[e] = l; }
+  }
+}
+
+hipError_t launch_init_identity(const double* g, int n, int np, float* z32, double* z64r,
+                                double* z64c, u16* zr_hi, u16* zr_lo, u16* zc_hi, u16* zc_lo,
+                                hipStream_t st) {
+  const size_t total = (size_t)np * np;
+  hipLaunchKernelGGL(init_identity_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, g, n, np,
+                     z32, z64r, z64c, zr_hi, zr_lo, zc_hi, zc_lo);
+  return hipGetLastError();
+}
+
+// Given Z0 (n x n, ld n): padded copies in row-major and transposed layouts.
+__global__ void init_given_kernel(const double* __restrict__ Z0, int n, int np, float* z32,
+                                  double* z64r, double* z64c, u16* zr_hi, u16* zr_lo, u16* zc_hi,
+                                  u16* zc_lo) {
+  const size_t total = (size_t)np * np;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / np), j = (int)(e % np);
+    const double v = (i < n && j < n) ? Z0[(size_t)i * n + j] : 0.0;
+    const float f = (float)v;
+    const size_t t = (size_t)j * np + i;
+    u16 h, l;
+    split_bf16(f, h, l);
+    if (z32) z32[e] = f;
+    if (z64r) z64r[e] = v;
+    if (z64c) z64c[t] = v;
+    if (zr_hi) { zr_hi[e] = h; zr_lo[e] = l; }
+    if (zc_hi) { zc_hi[t] = h; zc_lo[t] = l; }
+  }
+}
+
+hipError_t launch_init_given(const double* Z0, int n, int np, float* z32, double* z64r,
+                             double* z64c, u16* zr_hi, u16* zr_lo, u16* zc_hi, u16* zc_lo,
+                             hipStream_t st) {
+  const size_t total = (size_t)np * np;
+  hipLaunchKernelGGL(init_given_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, Z0, n, np,
+                     z32, z64r, z64c, zr_hi, zr_lo, zc_hi, zc_lo);
+  return hipGetLastError();
+}
+
+// FP32 master -> FP64 row-major and transposed (start of the refinement phase).
+__global__ void widen_kernel(const float* __restrict__ z32, int np, double* z64r, double* z64c) {
+  const size_t total = (size_t)np * np;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / np), j = (int)(e % np);
+    const double v = (double)z32[e];
+    z64r[e] = v;
+    z64c[(size_t)j * np + i] = v;
+  }
+}
+
+hipError_t launch_widen(const float* z32, int np, double* z64r, double* z64c, hipStream_t st) {
+  const size_t total = (size_t)np * np;
+  hipLaunchKernelGGL(widen_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, z32, np, z64r, z64c);
+  return hipGetLastError();
+}
+
+__global__ void unpad_f64_kernel(const double* __restrict__ src, int np, int n, double* __restrict__ dst) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    dst[e] = src[(size_t)i * np + j];
+  }
+}
+
+__global__ void unpad_f32_kernel(const float* __restrict__ src, int np, int n, double* __restrict__ dst) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    dst[e] = (double)src[(size_t)i * np + j];
+  }
+}
+
+hipError_t launch_unpad_f64(const double* src, int np, int n, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(unpad_f64_kernel, dim3(grid_for((size_t)n * n, 256)), dim3(256), 0, st, src, np,
+                     n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpad_f32(const float* src, int np, int n, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(unpad_f32_kernel, dim3(grid_for((size_t)n * n, 256)), dim3(256), 0, st, src, np,
+                     n, dst);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ||.||_F from per-tile partial sums: fixed summation order (bitwise repeatable).
+// ---------------------------------------------------------------------------
+__global__ void norm_finalize_kernel(const double* __restrict__ partials, int count, double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) s += partials[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(red[0]);
+}
+
+hipError_t launch_norm_finalize(const double* partials, int count, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(norm_finalize_kernel, dim3(1), dim3(256), 0, st, partials, count, out);
+  return hipGetLastError();
+}
+
+__global__ void fill_zero_kernel(uint32_t* p, size_t words) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < words;
+       e += (size_t)gridDim.x * blockDim.x)
+    p[e] = 0u;
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t words = bytes / 4;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(words, 256)), dim3(256), 0, st, (uint32_t*)p, words);
+  return hipGetLastError();
+}
+
+}  // namespace zf

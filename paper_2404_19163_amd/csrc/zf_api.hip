@@ -1,0 +1,756 @@
+// Host driver and C ABI of libzf (see include/zf.h).
+//
+// One call of zf_refine_ex runs
+//   setup:   split / pad S, form Z0 (given or I/sqrt(g), g the Gershgorin bound)
+//   phase L: low-precision sweeps under the stop test of Algorithm 2 (Sec. IV.A)
+//   phase H: FP64 residual sweeps (Sec. IV.B, Algorithm 3), ratio-stopped in FP64
+//   output:  Z (FP64, unpadded)
+// A sweep is: residual evaluation (GEMM1 A^T = Z^T S, GEMM2 delta = I - Z^T A,
+// both with Frobenius-norm partials) -> one double to the host -> stop test ->
+// correction Q = sum_{k>=1} c_k delta^k (m - 1 symmetric GEMMs, Horner) ->
+// GEMM4 Z_new = Z + Z Q into the other half of a ping-pong pair.
+//
+// All internal matrices are zero-padded to a multiple of the GEMM tile; the
+// identity of delta = I - X is restricted to the valid block, so the padding
+// stays exactly zero through every sweep (the zero padding of Sec. V.E without
+// its singular pad block).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "zf.h"
+#include "zf_internal.h"
+
+namespace zf {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return fail(ZF_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__,    \
+                  __LINE__);                                                                \
+  } while (0)
+
+#define ZF_TRY(expr)        \
+  do {                      \
+    int _r = (expr);        \
+    if (_r < 0) return _r;  \
+  } while (0)
+
+static int round_up(int n, int g) { return (n + g - 1) / g * g; }
+
+// ---------------------------------------------------------------------------
+// per-kernel timing (HIP events on the caller's stream)
+// ---------------------------------------------------------------------------
+enum KClass { K_X3 = 0, K_X3_SYM, K_F64, K_F64_SYM, K_COUNT };
+static const char* kClassName[K_COUNT] = {"gemm_x3", "gemm_x3_sym", "gemm_f64", "gemm_f64_sym"};
+
+struct PendingEvent {
+  hipEvent_t a, b;
+  int cls;
+  double flops;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<PendingEvent> pending;
+  long long launches[K_COUNT] = {};
+  double ms[K_COUNT] = {};
+  double flops[K_COUNT] = {};
+};
+static Profiler g_prof;
+
+static hipEvent_t take_event() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Harvest finished events (the caller has synchronized the stream).
+static void prof_harvest() {
+  for (auto& p : g_prof.pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+      g_prof.launches[p.cls] += 1;
+      g_prof.ms[p.cls] += t;
+      g_prof.flops[p.cls] += p.flops;
+    }
+    g_prof.pool.push_back(p.a);
+    g_prof.pool.push_back(p.b);
+  }
+  g_prof.pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+struct Workspace {
+  int device = -1;
+  int np = 0;
+  bool has_x3 = false, has_f64 = false;
+  std::vector<void*> allocs;
+  // x3 operands (BF16 hi/lo pairs)
+  u16 *s_hi = nullptr, *s_lo = nullptr;
+  u16 *zr_hi[2] = {}, *zr_lo[2] = {}, *zc_hi[2] = {}, *zc_lo[2] = {};
+  u16 *at_hi = nullptr, *at_lo = nullptr, *d_hi = nullptr, *d_lo = nullptr;
+  u16 *q_hi = nullptr, *q_lo = nullptr, *u_hi = nullptr, *u_lo = nullptr;
+  float* z32[2] = {};
+  // FP64
+  double *s64 = nullptr, *z64r[2] = {}, *z64c[2] = {}, *a64t = nullptr, *d64 = nullptr;
+  double *q64 = nullptr, *u64 = nullptr;
+  // scalars
+  double *partials = nullptr, *err_dev = nullptr, *rowsum = nullptr, *g_dev = nullptr;
+  double* host_err = nullptr;  // pinned
+};
+
+static Workspace g_ws;
+
+static void ws_free(Workspace& w) {
+  for (void* p : w.allocs) hipFree(p);
+  w.allocs.clear();
+  if (w.host_err) hipHostFree(w.host_err);
+  int dev = w.device;
+  w = Workspace();
+  w.device = dev;
+}
+
+template <typename T>
+static int ws_alloc(Workspace& w, T** out, size_t elems) {
+  void* p = nullptr;
+  const char* inject = getenv("ZF_FAULT_INJECT");
+  if (inject && strcmp(inject, "alloc") == 0)
+    return fail(ZF_ERR_NOMEM, "allocation of %zu bytes refused (ZF_FAULT_INJECT=alloc)",
+                elems * sizeof(T));
+  hipError_t e = hipMalloc(&p, elems * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ZF_ERR_NOMEM, "hipMalloc(%zu bytes): %s", elems * sizeof(T), hipGetErrorString(e));
+  }
+  w.allocs.push_back(p);
+  *out = (T*)p;
+  return 0;
+}
+
+static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Workspace& w = g_ws;
+  if (w.device != dev || w.np < np || (need_x3 && !w.has_x3) || (need_f64 && !w.has_f64)) {
+    const bool keep_x3 = (w.device == dev) && w.has_x3;
+    const bool keep_f64 = (w.device == dev) && w.has_f64;
+    const int np_new = (w.device == dev && w.np > np) ? w.np : np;
+    ws_free(w);
+    w.device = dev;
+    w.np = np_new;
+    const size_t m = (size_t)np_new * np_new;
+    const int tiles = num_tiles(np_new, np_new, false);
+    w.has_x3 = need_x3 || keep_x3;
+    w.has_f64 = need_f64 || keep_f64;
+    ZF_TRY(ws_alloc(w, &w.partials, tiles));
+    ZF_TRY(ws_alloc(w, &w.err_dev, 8));
+    ZF_TRY(ws_alloc(w, &w.rowsum, np_new));
+    ZF_TRY(ws_alloc(w, &w.g_dev, 8));
+    HIP_TRY(hipHostMalloc((void**)&w.host_err, 8 * sizeof(double), hipHostMallocDefault));
+    // the BF16 pairs of delta and Q and the row-major Z pair serve both phases
+    ZF_TRY(ws_alloc(w, &w.d_hi, m));
+    ZF_TRY(ws_alloc(w, &w.d_lo, m));
+    ZF_TRY(ws_alloc(w, &w.q_hi, m));
+    ZF_TRY(ws_alloc(w, &w.q_lo, m));
+    ZF_TRY(ws_alloc(w, &w.u_hi, m));
+    ZF_TRY(ws_alloc(w, &w.u_lo, m));
+    for (int b = 0; b < 2; ++b) {
+      ZF_TRY(ws_alloc(w, &w.zr_hi[b], m));
+      ZF_TRY(ws_alloc(w, &w.zr_lo[b], m));
+    }
+    if (w.has_x3) {
+      ZF_TRY(ws_alloc(w, &w.s_hi, m));
+      ZF_TRY(ws_alloc(w, &w.s_lo, m));
+      ZF_TRY(ws_alloc(w, &w.at_hi, m));
+      ZF_TRY(ws_alloc(w, &w.at_lo, m));
+      for (int b = 0; b < 2; ++b) {
+        ZF_TRY(ws_alloc(w, &w.zc_hi[b], m));
+        ZF_TRY(ws_alloc(w, &w.zc_lo[b], m));
+        ZF_TRY(ws_alloc(w, &w.z32[b], m));
+      }
+    }
+    if (w.has_f64) {
+      ZF_TRY(ws_alloc(w, &w.s64, m));
+      ZF_TRY(ws_alloc(w, &w.a64t, m));
+      ZF_TRY(ws_alloc(w, &w.d64, m));
+      ZF_TRY(ws_alloc(w, &w.q64, m));
+      ZF_TRY(ws_alloc(w, &w.u64, m));
+      for (int b = 0; b < 2; ++b) {
+        ZF_TRY(ws_alloc(w, &w.z64r[b], m));
+        ZF_TRY(ws_alloc(w, &w.z64c[b], m));
+      }
+    }
+  }
+  *out = &w;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM wrappers (timing + flop accounting)
+// ---------------------------------------------------------------------------
+static EpiParams epi0(int np, int n_valid) {
+  EpiParams e;
+  memset(&e, 0, sizeof e);
+  e.alpha = 0.0;
+  e.beta = 1.0;
+  e.gamma = 0.0;
+  e.ld = np;
+  e.n_valid = n_valid;
+  return e;
+}
+
+static int gemm_x3(const u16* Ah, const u16* Al, const u16* Bh, const u16* Bl, int np, bool sym,
+                   const EpiParams& ep, hipStream_t st) {
+  PendingEvent pe{};
+  const bool prof = g_prof.on;
+  if (prof) {
+    pe.a = take_event();
+    pe.b = take_event();
+    pe.cls = sym ? K_X3_SYM : K_X3;
+    // executed MFMA flops: 3 products of 2 * tile^3 per tile-step
+    pe.flops = 3.0 * 2.0 * (double)num_tiles(np, np, sym) * kTile * kTile * (double)np;
+    HIP_TRY(hipEventRecord(pe.a, st));
+  }
+  HIP_TRY(launch_gemm_x3(Ah, Al, np, Bh, Bl, np, np, np, np, sym, ep, st));
+  if (prof) {
+    HIP_TRY(hipEventRecord(pe.b, st));
+    g_prof.pending.push_back(pe);
+  }
+  return 0;
+}
+
+static int gemm_f64(const double* A, const double* B, int np, bool sym, const EpiParams& ep,
+                    hipStream_t st) {
+  PendingEvent pe{};
+  const bool prof = g_prof.on;
+  if (prof) {
+    pe.a = take_event();
+    pe.b = take_event();
+    pe.cls = sym ? K_F64_SYM : K_F64;
+    pe.flops = 2.0 * (double)num_tiles(np, np, sym) * kTile * kTile * (double)np;
+    HIP_TRY(hipEventRecord(pe.a, st));
+  }
+  HIP_TRY(launch_gemm_f64(A, np, B, np, np, np, np, sym, ep, st));
+  if (prof) {
+    HIP_TRY(hipEventRecord(pe.b, st));
+    g_prof.pending.push_back(pe);
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// the sweep
+// ---------------------------------------------------------------------------
+struct Ctx {
+  Workspace* w;
+  int n, np, order;
+  hipStream_t st;
+  double c[8];  // c_k = C(2k,k)/4^k
+};
+
+static void series(int m, double* c) {
+  // c_0 = 1, c_k = c_{k-1} (2k - 1) / (2k): the binomial series of (1 - d)^(-1/2)
+  c[0] = 1.0;
+  for (int k = 1; k <= m; ++k) c[k] = c[k - 1] * (2.0 * k - 1.0) / (2.0 * k);
+}
+
+// Frobenius norm of the last GEMM2's partials -> host
+static int fetch_err(Ctx& c, double* err) {
+  const int count = num_tiles(c.np, c.np, true);
+  HIP_TRY(launch_norm_finalize(c.w->partials, count, c.w->err_dev, c.st));
+  HIP_TRY(hipMemcpyAsync(c.w->host_err, c.w->err_dev, sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIP_TRY(hipStreamSynchronize(c.st));
+  *err = c.w->host_err[0];
+  return 0;
+}
+
+// residual evaluation of Z[cur]: writes delta (hi/lo and, if high, FP64) and Err
+static int delta_eval(Ctx& c, bool high, bool want_split, int cur, double* err) {
+  Workspace& w = *c.w;
+  const int np = c.np;
+  if (!high) {
+    EpiParams e1 = epi0(np, c.n);
+    e1.ohi = w.at_hi;
+    e1.olo = w.at_lo;
+    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.s_hi, w.s_lo, np, false, e1, c.st));
+    EpiParams e2 = epi0(np, c.n);
+    e2.beta = -1.0;
+    e2.gamma = 1.0;
+    e2.ohi = e2.othi = w.d_hi;
+    e2.olo = e2.otlo = w.d_lo;
+    e2.partials = w.partials;
+    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.at_hi, w.at_lo, np, true, e2, c.st));
+  } else {
+    EpiParams e1 = epi0(np, c.n);
+    e1.o64 = w.a64t;
+    ZF_TRY(gemm_f64(w.z64c[cur], w.s64, np, false, e1, c.st));
+    EpiParams e2 = epi0(np, c.n);
+    e2.beta = -1.0;
+    e2.gamma = 1.0;
+    e2.o64 = e2.ot64 = w.d64;
+    if (want_split) {
+      e2.ohi = e2.othi = w.d_hi;
+      e2.olo = e2.otlo = w.d_lo;
+    }
+    e2.partials = w.partials;
+    ZF_TRY(gemm_f64(w.z64c[cur], w.a64t, np, true, e2, c.st));
+  }
+  return fetch_err(c, err);
+}
+
+// Q = sum_{k=1..m} c_k delta^k by Horner over symmetric GEMMs (m >= 2).
+// Returns the BF16 pair (x3) or FP64 matrix holding Q.
+static int build_q(Ctx& c, bool x3, bool delta64, const u16** qh, const u16** ql, const double** q64) {
+  Workspace& w = *c.w;
+  const int np = c.np, m = c.order;
+  const u16 *bh = w.d_hi, *bl = w.d_lo;
+  const double* b64 = w.d64;
+  for (int k = m - 1; k >= 1; --k) {
+    EpiParams e = epi0(np, c.n);
+    e.alpha = c.c[k];
+    e.beta = (k == m - 1) ? c.c[m] : 1.0;
+    if (delta64) e.d64 = w.d64;
+    else { e.dhi = w.d_hi; e.dlo = w.d_lo; }
+    const bool to_q = (k % 2) == 1;
+    if (x3) {
+      u16* oh = to_q ? w.q_hi : w.u_hi;
+      u16* ol = to_q ? w.q_lo : w.u_lo;
+      e.ohi = e.othi = oh;
+      e.olo = e.otlo = ol;
+      ZF_TRY(gemm_x3(w.d_hi, w.d_lo, bh, bl, np, true, e, c.st));
+      bh = oh;
+      bl = ol;
+    } else {
+      double* o = to_q ? w.q64 : w.u64;
+      e.o64 = e.ot64 = o;
+      ZF_TRY(gemm_f64(w.d64, b64, np, true, e, c.st));
+      b64 = o;
+    }
+  }
+  *qh = bh;
+  *ql = bl;
+  *q64 = b64;
+  return 0;
+}
+
+// Z[cur] -> Z[cur ^ 1] = Z + Z Q
+static int update(Ctx& c, bool high, bool x3corr, int cur) {
+  Workspace& w = *c.w;
+  const int np = c.np, nxt = cur ^ 1;
+  const bool x3 = !high || x3corr;
+  const u16 *qh = w.d_hi, *ql = w.d_lo;
+  const double* q64 = w.d64;
+  double beta = 1.0;
+  if (c.order == 1) beta = c.c[1];  // Q = c_1 delta: fold the scale into GEMM4
+  else ZF_TRY(build_q(c, x3, high, &qh, &ql, &q64));
+  EpiParams e = epi0(np, c.n);
+  e.alpha = 1.0;
+  e.beta = beta;
+  if (!high) {
+    e.d32 = w.z32[cur];
+    e.o32 = w.z32[nxt];
+    e.ohi = w.zr_hi[nxt];
+    e.olo = w.zr_lo[nxt];
+    e.othi = w.zc_hi[nxt];
+    e.otlo = w.zc_lo[nxt];
+    return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], qh, ql, np, false, e, c.st);
+  }
+  e.d64 = w.z64r[cur];
+  e.o64 = w.z64r[nxt];
+  e.ot64 = w.z64c[nxt];
+  if (x3corr) {
+    e.ohi = w.zr_hi[nxt];
+    e.olo = w.zr_lo[nxt];
+    return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], qh, ql, np, false, e, c.st);
+  }
+  return gemm_f64(w.z64r[cur], q64, np, false, e, c.st);
+}
+
+struct PhaseOut {
+  int updates = 0;   // updates contained in the chosen iterate
+  int evals = 0;
+  double err = 0.0;  // Err of the chosen iterate
+  bool capped = false;
+};
+
+static int run_phase(Ctx& c, bool high, bool x3corr, int stop_rule, int max_updates, int& cur,
+                     std::vector<double>& hist, PhaseOut& out) {
+  double prev = 0.0;
+  for (int it = 0;; ++it) {
+    double err = 0.0;
+    ZF_TRY(delta_eval(c, high, high && x3corr, cur, &err));
+    out.evals++;
+    hist.push_back(err);
+    if (!isfinite(err))
+      return fail(ZF_ERR_NONFINITE, "residual norm is not finite at %s sweep %d",
+                  high ? "FP64" : "low-precision", it);
+    bool stop = false;
+    if (it > 0) {
+      if (stop_rule == ZF_STOP_MONOTONE) stop = err >= prev;
+      else stop = err > pow(prev, (double)(c.order + 1));
+    }
+    if (stop) {
+      if (err > prev) {  // the previous iterate is still in the other buffer
+        cur ^= 1;
+        out.updates = it - 1;
+        out.err = prev;
+      } else {
+        out.updates = it;
+        out.err = err;
+      }
+      return 0;
+    }
+    if (it >= max_updates) {
+      out.updates = it;
+      out.err = err;
+      out.capped = true;
+      return 0;
+    }
+    ZF_TRY(update(c, high, x3corr, cur));
+    cur ^= 1;
+    prev = err;
+  }
+}
+
+static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& o, double* Z,
+                       zf_result* res, double* hist, int hist_cap, hipStream_t st) {
+  if (!S || !Z) return fail(ZF_ERR_ARG, "S and Z must be non-NULL device pointers");
+  if (n <= 0) return fail(ZF_ERR_ARG, "n must be >= 1 (got %d)", n);
+  if (o.order < 1 || o.order > 5) return fail(ZF_ERR_ARG, "order must be in 1..5 (got %d)", o.order);
+  if (o.precision != ZF_FP64 && o.precision != ZF_BF16X3)
+    return fail(ZF_ERR_ARG, "precision %d is not supported", o.precision);
+  if (o.stop != ZF_STOP_RATIO && o.stop != ZF_STOP_MONOTONE)
+    return fail(ZF_ERR_ARG, "unknown stop rule %d", o.stop);
+  if (o.refine < ZF_REFINE_OFF || o.refine > ZF_REFINE_F64_FULL)
+    return fail(ZF_ERR_ARG, "unknown refine mode %d", o.refine);
+  if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(ZF_ERR_ARG, "bad hist buffer");
+  if (n > 46000) return fail(ZF_ERR_ARG, "n = %d exceeds the supported maximum 46000", n);
+
+  const bool mixed = o.precision != ZF_FP64;
+  const bool use_h = !mixed || o.refine != ZF_REFINE_OFF;
+  const bool x3corr = mixed && o.refine == ZF_REFINE_F64_DELTA;
+  const int np = round_up(n, kTile);
+  Workspace* w = nullptr;
+  ZF_TRY(ws_get(np, mixed, use_h, &w));
+
+  Ctx c;
+  c.w = w;
+  c.n = n;
+  c.np = np;
+  c.order = o.order;
+  c.st = st;
+  series(o.order, c.c);
+  const int max_l = o.max_sweeps > 0 ? o.max_sweeps : 100;
+  const int max_h = o.max_refine > 0 ? o.max_refine : 10;
+
+  // setup: operands of S, then Z0
+  HIP_TRY(launch_split_pad(S, n, n, np, mixed ? w->s_hi : nullptr, mixed ? w->s_lo : nullptr,
+                           use_h ? w->s64 : nullptr, nullptr, false, 1, st));
+  if (Z0) {
+    HIP_TRY(launch_init_given(Z0, n, np, mixed ? w->z32[0] : nullptr, use_h ? w->z64r[0] : nullptr,
+                              use_h ? w->z64c[0] : nullptr, w->zr_hi[0], w->zr_lo[0],
+                              mixed ? w->zc_hi[0] : nullptr, mixed ? w->zc_lo[0] : nullptr, st));
+  } else {
+    HIP_TRY(launch_row_abs_max(S, n, n, w->rowsum, w->g_dev, st));
+    HIP_TRY(launch_init_identity(w->g_dev, n, np, mixed ? w->z32[0] : nullptr,
+                                 use_h ? w->z64r[0] : nullptr, use_h ? w->z64c[0] : nullptr,
+                                 w->zr_hi[0], w->zr_lo[0], mixed ? w->zc_hi[0] : nullptr,
+                                 mixed ? w->zc_lo[0] : nullptr, st));
+  }
+
+  std::vector<double> h;
+  int cur = 0;
+  PhaseOut pl, ph;
+  int flags = 0;
+  int rc = 0;
+  if (mixed) {
+    rc = run_phase(c, false, false, o.stop, max_l, cur, h, pl);
+    if (rc < 0) goto done;
+    if (pl.capped) flags |= ZF_WARN_MAXSWEEPS;
+    if (use_h) {
+      HIP_TRY(launch_widen(w->z32[cur], np, w->z64r[cur], w->z64c[cur], st));
+      // the refinement phase always uses the ratio rule in FP64 (Sec. IV.B)
+      rc = run_phase(c, true, x3corr, o.stop, max_h, cur, h, ph);
+      if (rc < 0) goto done;
+      if (ph.capped) flags |= ZF_WARN_MAXSWEEPS;
+    }
+  } else {
+    rc = run_phase(c, true, false, o.stop, max_l, cur, h, ph);
+    if (rc < 0) goto done;
+    if (ph.capped) flags |= ZF_WARN_MAXSWEEPS;
+  }
+  if (use_h) HIP_TRY(launch_unpad_f64(w->z64r[cur], np, n, Z, st));
+  else HIP_TRY(launch_unpad_f32(w->z32[cur], np, n, Z, st));
+  HIP_TRY(hipStreamSynchronize(st));
+
+done:
+  if (g_prof.on) prof_harvest();
+  {
+    const int len = (int)h.size() < hist_cap ? (int)h.size() : hist_cap;
+    for (int i = 0; i < len; ++i) hist[i] = h[i];
+    if ((int)h.size() > hist_cap && hist_cap >= 0 && rc >= 0) flags |= ZF_WARN_HIST_TRUNC;
+    if (res) {
+      res->iters = pl.updates + ph.updates;
+      res->low_evals = pl.evals;
+      res->high_evals = ph.evals;
+      res->hist_len = len;
+      res->flags = flags;
+      res->final_err = use_h ? ph.err : pl.err;
+      res->final_rms = res->final_err / sqrt((double)n);
+    }
+  }
+  if (rc < 0) return rc;
+  const double fe = use_h ? ph.err : pl.err;
+  if (!(fe < 1.0))
+    return fail(ZF_ERR_NOT_CONVERGED,
+                "||Z^T S Z - I||_F = %g >= 1: the guess violates ||X0 - I||_2 < 1 or S is not SPD",
+                fe);
+  g_err.clear();
+  return flags;
+}
+
+}  // namespace zf
+
+using namespace zf;
+
+extern "C" {
+
+void zf_default_opts(zf_opts* o) {
+  if (!o) return;
+  o->order = 2;
+  o->precision = ZF_BF16X3;
+  o->stop = ZF_STOP_RATIO;
+  o->max_sweeps = 100;
+  o->refine = ZF_REFINE_F64_DELTA;
+  o->max_refine = 10;
+}
+
+int zf_refine_ex(const double* S, const double* Z0, int n, const zf_opts* opts, double* Z,
+                 zf_result* res, double* hist, int hist_cap, void* stream) {
+  zf_opts o;
+  zf_default_opts(&o);
+  if (opts) o = *opts;
+  return refine_impl(S, Z0, n, o, Z, res, hist, hist_cap, (hipStream_t)stream);
+}
+
+int zf_refine(const double* S, const double* Z0, int n, int order, int precision, double* Z,
+              int* iters, double* hist, int hist_cap, int* hist_len, void* stream) {
+  zf_opts o;
+  zf_default_opts(&o);
+  o.order = order;
+  o.precision = precision;
+  zf_result r;
+  memset(&r, 0, sizeof r);
+  const int rc = refine_impl(S, Z0, n, o, Z, &r, hist, hist_cap, (hipStream_t)stream);
+  if (iters) *iters = r.iters;
+  if (hist_len) *hist_len = r.hist_len;
+  return rc;
+}
+
+int zf_residual(const double* S, const double* Z, int n, double* err_f, void* stream) {
+  if (!S || !Z || !err_f) return fail(ZF_ERR_ARG, "NULL argument");
+  if (n <= 0) return fail(ZF_ERR_ARG, "n must be >= 1 (got %d)", n);
+  hipStream_t st = (hipStream_t)stream;
+  const int np = round_up(n, kTile);
+  Workspace* w = nullptr;
+  ZF_TRY(ws_get(np, false, true, &w));
+  Ctx c;
+  c.w = w;
+  c.n = n;
+  c.np = np;
+  c.order = 2;
+  c.st = st;
+  series(2, c.c);
+  HIP_TRY(launch_split_pad(S, n, n, np, nullptr, nullptr, w->s64, nullptr, false, 1, st));
+  HIP_TRY(launch_init_given(Z, n, np, nullptr, w->z64r[0], w->z64c[0], w->zr_hi[0], w->zr_lo[0],
+                            nullptr, nullptr, st));
+  double e = 0.0;
+  ZF_TRY(delta_eval(c, true, false, 0, &e));
+  if (g_prof.on) prof_harvest();
+  *err_f = e;
+  g_err.clear();
+  return 0;
+}
+
+void zf_release(void) {
+  if (g_ws.device >= 0) ws_free(g_ws);
+  g_ws.device = -1;
+  for (auto& p : g_prof.pending) {
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  g_prof.pending.clear();
+  for (auto e : g_prof.pool) hipEventDestroy(e);
+  g_prof.pool.clear();
+}
+
+const char* zf_last_error(void) { return g_err.c_str(); }
+
+int zf_version(void) { return 1; }
+
+// ---- per-kernel timing ------------------------------------------------------
+void zf_profile_enable(int on) { g_prof.on = on != 0; }
+
+void zf_profile_reset(void) {
+  for (int k = 0; k < K_COUNT; ++k) {
+    g_prof.launches[k] = 0;
+    g_prof.ms[k] = 0.0;
+    g_prof.flops[k] = 0.0;
+  }
+}
+
+int zf_profile_read(int cls, const char** name, long long* launches, double* total_ms,
+                    double* flops) {
+  if (cls < 0 || cls >= K_COUNT) return fail(ZF_ERR_ARG, "kernel class %d out of range", cls);
+  if (name) *name = kClassName[cls];
+  if (launches) *launches = g_prof.launches[cls];
+  if (total_ms) *total_ms = g_prof.ms[cls];
+  if (flops) *flops = g_prof.flops[cls];
+  return 0;
+}
+
+// ---- kernel-level test entry points -----------------------------------------
+int zf_t_split(const double* a, int64_t count, uint16_t* hi, uint16_t* lo, int fmt, void* stream) {
+  if (count < 0) return fail(ZF_ERR_ARG, "negative count");
+  if (fmt != 1 && fmt != 2) return fail(ZF_ERR_ARG, "fmt must be 1 (BF16) or 2 (FP16)");
+  if (count == 0) return 0;
+  if (!a || !hi || !lo) return fail(ZF_ERR_ARG, "NULL split buffer");
+  HIP_TRY(launch_split_flat(a, count, hi, lo, fmt, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return 0;
+}
+
+int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, const double* B,
+              double alpha, const double* D, double beta, double gamma, double* C, double* norm_sq,
+              void* stream) {
+  if (!A || !B || !C || m <= 0 || nn <= 0 || k <= 0) return fail(ZF_ERR_ARG, "bad gemm arguments");
+  if (sym && m != nn) return fail(ZF_ERR_ARG, "symmetric mode needs m == nn");
+  if (precision != ZF_FP64 && precision != ZF_BF16X3)
+    return fail(ZF_ERR_ARG, "precision %d not supported", precision);
+  hipStream_t st = (hipStream_t)stream;
+  // pad every operand to a common square tile multiple
+  int np = m > nn ? m : nn;
+  if (k > np) np = k;
+  np = round_up(np, kTile);
+  const size_t e = (size_t)np * np;
+  std::vector<void*> tmp;
+  auto alloc = [&](size_t bytes, void** p) -> int {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ZF_ERR_NOMEM, "hipMalloc(%zu) failed", bytes);
+    }
+    tmp.push_back(*p);
+    return 0;
+  };
+  auto cleanup = [&]() {
+    for (void* p : tmp) hipFree(p);
+  };
+  double *a64, *b64, *c64, *d64 = nullptr, *part;
+  int rc = 0;
+  if ((rc = alloc(e * 8, (void**)&a64)) || (rc = alloc(e * 8, (void**)&b64)) ||
+      (rc = alloc(e * 8, (void**)&c64)) || (rc = alloc(num_tiles(np, np, false) * 8, (void**)&part)) ||
+      (D && (rc = alloc(e * 8, (void**)&d64)))) {
+    cleanup();
+    return rc;
+  }
+  hipError_t he = hipSuccess;
+  auto pad_in = [&](const double* src, int rows, int cols, double* dst) {
+    if (he != hipSuccess) return;
+    he = hipMemsetAsync(dst, 0, e * 8, st);
+    if (he == hipSuccess)
+      he = hipMemcpy2DAsync(dst, (size_t)np * 8, src, (size_t)cols * 8, (size_t)cols * 8, rows,
+                            hipMemcpyDeviceToDevice, st);
+  };
+  pad_in(A, m, k, a64);
+  pad_in(B, nn, k, b64);
+  if (D) pad_in(D, m, nn, d64);
+  if (he == hipSuccess) he = hipMemsetAsync(c64, 0, e * 8, st);
+  EpiParams ep = epi0(np, m < nn ? m : nn);
+  ep.alpha = alpha;
+  ep.beta = beta;
+  ep.gamma = gamma;
+  ep.d64 = d64;
+  ep.o64 = c64;
+  if (sym) ep.ot64 = c64;
+  ep.partials = part;
+  u16 *ah = nullptr, *al = nullptr, *bh = nullptr, *bl = nullptr;
+  if (he == hipSuccess && precision == ZF_BF16X3) {
+    if ((rc = alloc(e * 2, (void**)&ah)) || (rc = alloc(e * 2, (void**)&al)) ||
+        (rc = alloc(e * 2, (void**)&bh)) || (rc = alloc(e * 2, (void**)&bl))) {
+      cleanup();
+      return rc;
+    }
+    he = launch_split_flat(a64, (int64_t)e, ah, al, 1, st);
+    if (he == hipSuccess) he = launch_split_flat(b64, (int64_t)e, bh, bl, 1, st);
+    if (he == hipSuccess) he = launch_gemm_x3(ah, al, np, bh, bl, np, np, np, np, sym != 0, ep, st);
+  } else if (he == hipSuccess) {
+    he = launch_gemm_f64(a64, np, b64, np, np, np, np, sym != 0, ep, st);
+  }
+  double* nrm = nullptr;
+  if (he == hipSuccess && norm_sq) {
+    if ((rc = alloc(8, (void**)&nrm))) {
+      cleanup();
+      return rc;
+    }
+    he = launch_norm_finalize(part, num_tiles(np, np, sym != 0), nrm, st);
+  }
+  if (he == hipSuccess)
+    he = hipMemcpy2DAsync(C, (size_t)nn * 8, c64, (size_t)np * 8, (size_t)nn * 8, m,
+                          hipMemcpyDeviceToDevice, st);
+  double nv = 0.0;
+  if (he == hipSuccess && norm_sq) he = hipMemcpyAsync(&nv, nrm, 8, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  cleanup();
+  if (he != hipSuccess) return fail(ZF_ERR_HIP, "zf_t_gemm: %s", hipGetErrorString(he));
+  if (norm_sq) *norm_sq = nv * nv;
+  return 0;
+}
+
+int zf_t_gershgorin(const double* S, int n, double* g, void* stream) {
+  if (!S || !g || n <= 0) return fail(ZF_ERR_ARG, "bad gershgorin arguments");
+  hipStream_t st = (hipStream_t)stream;
+  double *rs = nullptr, *gd = nullptr;
+  if (hipMalloc((void**)&rs, (size_t)n * 8) != hipSuccess) return fail(ZF_ERR_NOMEM, "hipMalloc");
+  if (hipMalloc((void**)&gd, 8) != hipSuccess) {
+    hipFree(rs);
+    return fail(ZF_ERR_NOMEM, "hipMalloc");
+  }
+  hipError_t he = launch_row_abs_max(S, n, n, rs, gd, st);
+  double v = 0.0;
+  if (he == hipSuccess) he = hipMemcpyAsync(&v, gd, 8, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  hipFree(rs);
+  hipFree(gd);
+  if (he != hipSuccess) return fail(ZF_ERR_HIP, "zf_t_gershgorin: %s", hipGetErrorString(he));
+  *g = v;
+  return 0;
+}
+
+}  // extern "C"

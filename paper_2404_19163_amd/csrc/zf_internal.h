@@ -1,0 +1,104 @@
+// Internal declarations shared by the libzf translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace zf {
+
+typedef uint16_t u16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// FP32 -> BF16 with round to nearest, ties to even (NaN kept quiet).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u16 f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u16)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(u16 h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// FP32 -> FP16 (IEEE binary16) with round to nearest even, via the hardware convert.
+__device__ __forceinline__ u16 f32_to_f16_rne(float f) {
+  _Float16 h = (_Float16)f;
+  return *reinterpret_cast<u16*>(&h);
+}
+__device__ __forceinline__ float f16_to_f32(u16 b) {
+  _Float16 h;
+  *reinterpret_cast<u16*>(&h) = b;
+  return (float)h;
+}
+
+// Two-term split of Sec. III.A: hi = LP[x], lo = LP[x - hi]; x - hi is exact in FP32.
+__device__ __forceinline__ void split_bf16(float x, u16& hi, u16& lo) {
+  hi = f32_to_bf16_rne(x);
+  lo = f32_to_bf16_rne(x - bf16_to_f32(hi));
+}
+__device__ __forceinline__ void split_f16(float x, u16& hi, u16& lo) {
+  hi = f32_to_f16_rne(x);
+  lo = f32_to_f16_rne(x - f16_to_f32(hi));
+}
+
+// ---------------------------------------------------------------------------
+// GEMM epilogue: out = alpha * D + beta * acc + gamma * I  (I restricted to the
+// valid n_valid x n_valid block so that zero padding stays exactly zero).
+// Every output pointer is optional.  Normal outputs are written at
+// [row * ld + col]; transposed outputs at [col * ld + row].  In symmetric mode
+// the caller passes the same matrices for both, and the kernel writes the upper
+// triangle normally and mirrors it.
+// ---------------------------------------------------------------------------
+struct EpiParams {
+  double alpha, beta, gamma;
+  int n_valid;
+  int ld;
+  const float* d32;
+  const double* d64;
+  const u16* dhi;
+  const u16* dlo;
+  float* o32;
+  double* o64;
+  u16* ohi;
+  u16* olo;
+  float* ot32;
+  double* ot64;
+  u16* othi;
+  u16* otlo;
+  double* partials;  // per-tile sum of out^2 (FP64), or nullptr
+};
+
+// Launchers (return hipSuccess or the launch error).  All dimensions must be
+// multiples of kTile; the caller pads.  Symmetric mode requires M == N.
+constexpr int kTile = 128;
+int num_tiles(int M, int N, bool sym);
+
+hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
+                          int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
+                          hipStream_t st);
+hipError_t launch_gemm_f64(const double* A, int lda, const double* B, int ldb, int M, int N, int K,
+                           bool sym, const EpiParams& ep, hipStream_t st);
+
+// Elementwise / reduction kernels (elementwise.hip)
+hipError_t launch_split_pad(const double* src, int n, int ld_src, int np, u16* hi, u16* lo,
+                            double* copy64, float* copy32, bool transpose_copy, int fmt,
+                            hipStream_t st);
+hipError_t launch_split_flat(const double* src, int64_t count, u16* hi, u16* lo, int fmt,
+                             hipStream_t st);
+hipError_t launch_row_abs_max(const double* S, int n, int ld, double* row_sums, double* g_out,
+                              hipStream_t st);
+hipError_t launch_init_identity(const double* g, int n, int np, float* z32, double* z64r,
+                                double* z64c, u16* zr_hi, u16* zr_lo, u16* zc_hi, u16* zc_lo,
+                                hipStream_t st);
+hipError_t launch_init_given(const double* Z0, int n, int np, float* z32, double* z64r,
+                             double* z64c, u16* zr_hi, u16* zr_lo, u16* zc_hi, u16* zc_lo,
+                             hipStream_t st);
+hipError_t launch_widen(const float* z32, int np, double* z64r, double* z64c, hipStream_t st);
+hipError_t launch_unpad_f64(const double* src, int np, int n, double* dst, hipStream_t st);
+hipError_t launch_unpad_f32(const float* src, int np, int n, double* dst, hipStream_t st);
+hipError_t launch_norm_finalize(const double* partials, int count, double* out, hipStream_t st);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace zf
