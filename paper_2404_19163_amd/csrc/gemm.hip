@@ -20,6 +20,8 @@
 // any of: FP32, FP64, a BF16 hi/lo split (Sec. III.A), each in normal and/or
 // transposed layout, plus a per-tile FP64 sum of out^2 for the Frobenius norm
 // of the stop test (Sec. IV.A).
+#include <stdlib.h>
+
 #include "zf_internal.h"
 
 namespace zf {
@@ -128,6 +130,47 @@ __device__ __forceinline__ void epi_group(const EpiParams& ep, int row0, int col
   }
 }
 
+// One output element of the LDS-staged epilogue: value = alpha D + beta acc +
+// gamma I in FP64.  normal != 0 writes the normal-layout outputs (and adds the
+// element's weight to nsum); normal == 0 writes the transposed outputs.
+__device__ __forceinline__ void epi_elem(const EpiParams& ep, int row, int col, float accv, int mode,
+                                         int normal, double& nsum) {
+  if (normal) {
+    if (mode == 2 && row > col) return;
+  } else {
+    if (mode == 2 && row >= col) return;
+  }
+  const size_t idx = (size_t)row * ep.ld + col;
+  double x = ep.beta * (double)accv;
+  if (ep.d64) x += ep.alpha * ep.d64[idx];
+  else if (ep.d32) x += ep.alpha * (double)ep.d32[idx];
+  else if (ep.dhi) x += ep.alpha * ((double)bf16_to_f32(ep.dhi[idx]) + (double)bf16_to_f32(ep.dlo[idx]));
+  if (row == col && row < ep.n_valid) x += ep.gamma;
+  const float f = (float)x;
+  if (normal) {
+    const double w = (mode == 0) ? 1.0 : ((mode == 1 || row < col) ? 2.0 : 1.0);
+    nsum += w * x * x;
+    if (ep.o64) ep.o64[idx] = x;
+    if (ep.o32) ep.o32[idx] = f;
+    if (ep.ohi) {
+      u16 h, l;
+      split_bf16(f, h, l);
+      ep.ohi[idx] = h;
+      ep.olo[idx] = l;
+    }
+  } else {
+    const size_t t = (size_t)col * ep.ld + row;
+    if (ep.ot64) ep.ot64[t] = x;
+    if (ep.ot32) ep.ot32[t] = f;
+    if (ep.othi) {
+      u16 h, l;
+      split_bf16(f, h, l);
+      ep.othi[t] = h;
+      ep.otlo[t] = l;
+    }
+  }
+}
+
 template <int NT>
 __device__ __forceinline__ void block_norm_store(double nsum, double* partials, int tile_id,
                                                  double* red) {
@@ -152,14 +195,23 @@ struct X3Cfg {
   static constexpr int NT = WM * WN * 64;
   static constexpr int WTM = BM / WM, WTN = BN / WN;
   static constexpr int FM = WTM / 32, FN = WTN / 32;
-  static constexpr int LS = BK + 8;  // LDS row stride in 16-bit elements (16-byte pad)
-  static constexpr int VPR = BK / 8;  // 16-byte vectors per tile row
+  static constexpr int VPR = BK / 8;  // 16-byte chunks per tile row
   static constexpr int A_PT = BM * VPR / NT, B_PT = BN * VPR / NT;
-  static constexpr int STAGE = (BM + BN) * 2 * LS;  // elements per pipeline stage
+  static constexpr int STAGE = (BM + BN) * 2 * BK;  // 16-bit elements per pipeline stage
+  static constexpr int SP = BN + 1;                  // epilogue strip pitch (floats)
+  static constexpr int LDS_BYTES = (2 * STAGE * 2 > WTM * SP * 4) ? 2 * STAGE * 2 : WTM * SP * 4;
+  static_assert(BK == 32, "the LDS swizzle assumes 64-byte tile rows");
   static_assert(BM % (WM * 32) == 0 && BN % (WN * 32) == 0, "wave tile");
-  static_assert(BK % 16 == 0, "k step");
   static_assert((BM * VPR) % NT == 0 && (BN * VPR) % NT == 0, "load split");
 };
+
+// Element offset of logical 16-byte chunk c of tile row r in an unpadded LDS tile
+// with 64-byte rows.  Chunk c sits at c ^ f(r), f(r) = ((r >> 1) ^ (r >> 3)) & 3:
+// one logical chunk of any 8 aligned consecutive rows (an 8-lane phase over 32
+// banks) and of any 16 (a 16-lane phase over 64 banks) lands on distinct banks.
+__device__ __forceinline__ int swz64(int r, int c) {
+  return r * 32 + ((c ^ (((r >> 1) ^ (r >> 3)) & 3)) << 3);
+}
 
 template <int BM, int BN, int BK, int WM, int WN>
 __global__ void __launch_bounds__(WM* WN * 64)
@@ -167,7 +219,7 @@ __global__ void __launch_bounds__(WM* WN * 64)
                    const u16* __restrict__ Bhi, const u16* __restrict__ Blo, int ldb, int K,
                    int tiles_n, int sym, EpiParams ep) {
   using C = X3Cfg<BM, BN, BK, WM, WN>;
-  __shared__ __attribute__((aligned(16))) u16 lds[2 * C::STAGE];
+  __shared__ __attribute__((aligned(16))) u16 lds[C::LDS_BYTES / 2];
   __shared__ double red[C::NT / 64];
 
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -177,41 +229,22 @@ __global__ void __launch_bounds__(WM* WN * 64)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
 
-  uint4 ra_h[C::A_PT], ra_l[C::A_PT], rb_h[C::B_PT], rb_l[C::B_PT];
-  auto gload = [&](int k0) {
+  // Global -> register -> LDS staging, one K block ahead.  Written as plain
+  // unrolled loops over constant indices so the staging arrays stay in VGPRs.
+  uint4 pa_h[C::A_PT], pa_l[C::A_PT], pb_h[C::B_PT], pb_l[C::B_PT];
+  int a_off[C::A_PT], b_off[C::B_PT], a_lds[C::A_PT], b_lds[C::B_PT];
 #pragma unroll
-    for (int i = 0; i < C::A_PT; ++i) {
-      const int v = tid + i * C::NT, r = v / C::VPR, c = v % C::VPR;
-      const size_t off = (size_t)(m0 + r) * lda + k0 + c * 8;
-      ra_h[i] = *reinterpret_cast<const uint4*>(Ahi + off);
-      ra_l[i] = *reinterpret_cast<const uint4*>(Alo + off);
-    }
+  for (int i = 0; i < C::A_PT; ++i) {
+    const int v = tid + i * C::NT, r = v / C::VPR, c = v % C::VPR;
+    a_off[i] = (m0 + r) * lda + c * 8;
+    a_lds[i] = swz64(r, c);
+  }
 #pragma unroll
-    for (int i = 0; i < C::B_PT; ++i) {
-      const int v = tid + i * C::NT, r = v / C::VPR, c = v % C::VPR;
-      const size_t off = (size_t)(n0 + r) * ldb + k0 + c * 8;
-      rb_h[i] = *reinterpret_cast<const uint4*>(Bhi + off);
-      rb_l[i] = *reinterpret_cast<const uint4*>(Blo + off);
-    }
-  };
-  auto sstore = [&](int s) {
-    u16* as_h = lds + s * C::STAGE;
-    u16* as_l = as_h + BM * C::LS;
-    u16* bs_h = as_l + BM * C::LS;
-    u16* bs_l = bs_h + BN * C::LS;
-#pragma unroll
-    for (int i = 0; i < C::A_PT; ++i) {
-      const int v = tid + i * C::NT, r = v / C::VPR, c = v % C::VPR;
-      *reinterpret_cast<uint4*>(as_h + r * C::LS + c * 8) = ra_h[i];
-      *reinterpret_cast<uint4*>(as_l + r * C::LS + c * 8) = ra_l[i];
-    }
-#pragma unroll
-    for (int i = 0; i < C::B_PT; ++i) {
-      const int v = tid + i * C::NT, r = v / C::VPR, c = v % C::VPR;
-      *reinterpret_cast<uint4*>(bs_h + r * C::LS + c * 8) = rb_h[i];
-      *reinterpret_cast<uint4*>(bs_l + r * C::LS + c * 8) = rb_l[i];
-    }
-  };
+  for (int i = 0; i < C::B_PT; ++i) {
+    const int v = tid + i * C::NT, r = v / C::VPR, c = v % C::VPR;
+    b_off[i] = (n0 + r) * ldb + c * 8;
+    b_lds[i] = swz64(r, c);
+  }
 
   f32x16 acc[C::FM][C::FN];
 #pragma unroll
@@ -220,62 +253,132 @@ __global__ void __launch_bounds__(WM* WN * 64)
     for (int b = 0; b < C::FN; ++b) acc[a][b] = f32x16{};
 
   const int KT = K / BK;
-  gload(0);
-  sstore(0);
+#pragma unroll
+  for (int i = 0; i < C::A_PT; ++i) {
+    pa_h[i] = *reinterpret_cast<const uint4*>(Ahi + a_off[i]);
+    pa_l[i] = *reinterpret_cast<const uint4*>(Alo + a_off[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < C::B_PT; ++i) {
+    pb_h[i] = *reinterpret_cast<const uint4*>(Bhi + b_off[i]);
+    pb_l[i] = *reinterpret_cast<const uint4*>(Blo + b_off[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < C::A_PT; ++i) {
+    *reinterpret_cast<uint4*>(lds + a_lds[i]) = pa_h[i];
+    *reinterpret_cast<uint4*>(lds + BM * BK + a_lds[i]) = pa_l[i];
+  }
+#pragma unroll
+  for (int i = 0; i < C::B_PT; ++i) {
+    *reinterpret_cast<uint4*>(lds + 2 * BM * BK + b_lds[i]) = pb_h[i];
+    *reinterpret_cast<uint4*>(lds + 2 * BM * BK + BN * BK + b_lds[i]) = pb_l[i];
+  }
   __syncthreads();
+
   for (int kt = 0; kt < KT; ++kt) {
     const int s = kt & 1;
-    if (kt + 1 < KT) gload((kt + 1) * BK);
+    // next K block; the last iteration re-reads its own block into the idle stage
+    const int kn = (kt + 1 < KT ? kt + 1 : kt) * BK;
+#pragma unroll
+    for (int i = 0; i < C::A_PT; ++i) {
+      pa_h[i] = *reinterpret_cast<const uint4*>(Ahi + a_off[i] + kn);
+      pa_l[i] = *reinterpret_cast<const uint4*>(Alo + a_off[i] + kn);
+    }
+#pragma unroll
+    for (int i = 0; i < C::B_PT; ++i) {
+      pb_h[i] = *reinterpret_cast<const uint4*>(Bhi + b_off[i] + kn);
+      pb_l[i] = *reinterpret_cast<const uint4*>(Blo + b_off[i] + kn);
+    }
     const u16* as_h = lds + s * C::STAGE;
-    const u16* as_l = as_h + BM * C::LS;
-    const u16* bs_h = as_l + BM * C::LS;
-    const u16* bs_l = bs_h + BN * C::LS;
+    const u16* as_l = as_h + BM * BK;
+    const u16* bs_h = as_l + BM * BK;
+    const u16* bs_l = bs_h + BN * BK;
 #pragma unroll
     for (int kk = 0; kk < BK / 16; ++kk) {
-      const int kc = kk * 16 + (lane >> 5) * 8;
-      bf16x8 ah[C::FM], al[C::FM], bh[C::FN], bl[C::FN];
+      const int ch = kk * 2 + (lane >> 5);  // logical 16-byte chunk of this lane's 8 K values
+      // Fragments are read per product pass (hh, hl, lh) so that only three of
+      // the four operand halves are live at once; consecutive MFMAs never
+      // update the same accumulator.
+      int ao[C::FM], bo[C::FN];
 #pragma unroll
-      for (int a = 0; a < C::FM; ++a) {
-        const int r = wm * C::WTM + a * 32 + (lane & 31);
-        ah[a] = *reinterpret_cast<const bf16x8*>(as_h + r * C::LS + kc);
-        al[a] = *reinterpret_cast<const bf16x8*>(as_l + r * C::LS + kc);
-      }
+      for (int a = 0; a < C::FM; ++a) ao[a] = swz64(wm * C::WTM + a * 32 + (lane & 31), ch);
 #pragma unroll
-      for (int b = 0; b < C::FN; ++b) {
-        const int r = wn * C::WTN + b * 32 + (lane & 31);
-        bh[b] = *reinterpret_cast<const bf16x8*>(bs_h + r * C::LS + kc);
-        bl[b] = *reinterpret_cast<const bf16x8*>(bs_l + r * C::LS + kc);
-      }
+      for (int b = 0; b < C::FN; ++b) bo[b] = swz64(wn * C::WTN + b * 32 + (lane & 31), ch);
+      bf16x8 ah[C::FM], bx[C::FN];
+#pragma unroll
+      for (int a = 0; a < C::FM; ++a) ah[a] = *reinterpret_cast<const bf16x8*>(as_h + ao[a]);
+#pragma unroll
+      for (int b = 0; b < C::FN; ++b) bx[b] = *reinterpret_cast<const bf16x8*>(bs_h + bo[b]);
 #pragma unroll
       for (int a = 0; a < C::FM; ++a)
 #pragma unroll
-        for (int b = 0; b < C::FN; ++b) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < C::FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bx[b], acc[a][b], 0, 0, 0);
+      bf16x8 bl[C::FN];
+#pragma unroll
+      for (int b = 0; b < C::FN; ++b) bl[b] = *reinterpret_cast<const bf16x8*>(bs_l + bo[b]);
+#pragma unroll
+      for (int a = 0; a < C::FM; ++a)
+#pragma unroll
+        for (int b = 0; b < C::FN; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-        }
+#pragma unroll
+      for (int a = 0; a < C::FM; ++a) ah[a] = *reinterpret_cast<const bf16x8*>(as_l + ao[a]);
+#pragma unroll
+      for (int a = 0; a < C::FM; ++a)
+#pragma unroll
+        for (int b = 0; b < C::FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bx[b], acc[a][b], 0, 0, 0);
     }
-    if (kt + 1 < KT) sstore(s ^ 1);
+    u16* ns = lds + (s ^ 1) * C::STAGE;
+#pragma unroll
+    for (int i = 0; i < C::A_PT; ++i) {
+      *reinterpret_cast<uint4*>(ns + a_lds[i]) = pa_h[i];
+      *reinterpret_cast<uint4*>(ns + BM * BK + a_lds[i]) = pa_l[i];
+    }
+#pragma unroll
+    for (int i = 0; i < C::B_PT; ++i) {
+      *reinterpret_cast<uint4*>(ns + 2 * BM * BK + b_lds[i]) = pb_h[i];
+      *reinterpret_cast<uint4*>(ns + 2 * BM * BK + BN * BK + b_lds[i]) = pb_l[i];
+    }
     __syncthreads();
   }
 
-  // epilogue: lane holds rows 8*(r/4) + 4*(lane/32) + r%4, column lane%32 of each 32x32 block
+  // Epilogue through LDS, one wave row (WTM x BN strip) at a time.  A lane holds
+  // rows 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32 of each 32x32 block;
+  // the strip is then walked row-major (normal outputs, coalesced) and
+  // column-major (transposed / mirrored outputs, coalesced).
   const int mode = sym ? (ti == tj ? 2 : 1) : 0;
+  const bool any_t = ep.ot64 || ep.ot32 || ep.othi;
+  float* strip = reinterpret_cast<float*>(lds);
   double nsum = 0.0;
+  for (int wr = 0; wr < WM; ++wr) {
+    __syncthreads();
+    if (wm == wr) {
 #pragma unroll
-  for (int a = 0; a < C::FM; ++a)
+      for (int a = 0; a < C::FM; ++a)
 #pragma unroll
-    for (int b = 0; b < C::FN; ++b) {
-      const int col = n0 + wn * C::WTN + b * 32 + (lane & 31);
+        for (int b = 0; b < C::FN; ++b)
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int row0 = m0 + wm * C::WTM + a * 32 + g * 8 + (lane >> 5) * 4;
-        double v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = (double)acc[a][b][g * 4 + q];
-        epi_group(ep, row0, col, v, mode, nsum);
+          for (int r = 0; r < 16; ++r) {
+            const int lr = a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int lc = wn * C::WTN + b * 32 + (lane & 31);
+            strip[lr * C::SP + lc] = acc[a][b][r];
+          }
+    }
+    __syncthreads();
+    const int row0 = m0 + wr * C::WTM;
+    for (int e = tid; e < C::WTM * BN; e += C::NT) {
+      const int lr = e / BN, lc = e % BN;
+      epi_elem(ep, row0 + lr, n0 + lc, strip[lr * C::SP + lc], mode, 1, nsum);
+    }
+    if (any_t) {
+      for (int e = tid; e < C::WTM * BN; e += C::NT) {
+        const int lr = e % C::WTM, lc = e / C::WTM;
+        epi_elem(ep, row0 + lr, n0 + lc, strip[lr * C::SP + lc], mode, 0, nsum);
       }
     }
+  }
   if (ep.partials) block_norm_store<C::NT>(nsum, ep.partials, blockIdx.x, red);
 }
 
@@ -297,7 +400,7 @@ struct F64Cfg {
 };
 
 template <int BM, int BN, int BK, int WM, int WN>
-__global__ void __launch_bounds__(WM* WN * 64)
+__global__ void __launch_bounds__(WM* WN * 64, 2)
     gemm_f64_kernel(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
                     int K, int tiles_n, int sym, EpiParams ep) {
   using C = F64Cfg<BM, BN, BK, WM, WN>;
@@ -407,15 +510,37 @@ static bool dims_ok(int M, int N, int K, bool sym) {
          (!sym || M == N);
 }
 
+// Tile edge for the (h)(h)+(h)(l)+(l)(h) kernel: 256 (8 waves) when both output
+// dimensions allow it, else 128 (4 waves).  ZF_X3_TILE / ZF_X3_SYM_TILE = 128 or
+// 256 override the choice for plain / symmetric launches (tuning only).
+int x3_tile(int M, int N, bool sym) {
+  const char* env = getenv(sym ? "ZF_X3_SYM_TILE" : "ZF_X3_TILE");
+  const int want = env ? atoi(env) : 256;
+  if (want == 256 && M % 256 == 0 && N % 256 == 0) return 256;
+  return 128;
+}
+
+int x3_blocks(int M, int N, bool sym) {
+  const int t = x3_tile(M, N, sym);
+  const int tm = M / t, tn = N / t;
+  return sym ? tm * (tm + 1) / 2 : tm * tn;
+}
+
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
                           hipStream_t st) {
   if (!dims_ok(M, N, K, sym)) return hipErrorInvalidValue;
-  constexpr int BM = 128, BN = 128, BK = 32, WM = 2, WN = 2;
-  static_assert(BM == kTile && BN == kTile, "padding granule");
-  const int blocks = num_tiles(M, N, sym);
-  hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0, st,
-                     Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym ? 1 : 0, ep);
+  const int tile = x3_tile(M, N, sym);
+  const int blocks = x3_blocks(M, N, sym);
+  if (tile == 256) {
+    constexpr int BM = 256, BN = 256, BK = 32, WM = 2, WN = 4;
+    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
+                       st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym ? 1 : 0, ep);
+  } else {
+    constexpr int BM = 128, BN = 128, BK = 32, WM = 2, WN = 2;
+    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
+                       st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym ? 1 : 0, ep);
+  }
   return hipGetLastError();
 }
 

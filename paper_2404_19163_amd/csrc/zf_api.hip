@@ -56,6 +56,10 @@ static int fail(int code, const char* fmt, ...) {
 
 static int round_up(int n, int g) { return (n + g - 1) / g * g; }
 
+// Padded order: a multiple of 256 from n = 1024 on (the 256-wide BF16x3 tiles), else
+// of 128 (every kernel's minimum tile).
+static int pad_order(int n) { return n >= 1024 ? round_up(n, 256) : round_up(n, kTile); }
+
 // ---------------------------------------------------------------------------
 // per-kernel timing (HIP events on the caller's stream)
 // ---------------------------------------------------------------------------
@@ -234,8 +238,9 @@ static int gemm_x3(const u16* Ah, const u16* Al, const u16* Bh, const u16* Bl, i
     pe.a = take_event();
     pe.b = take_event();
     pe.cls = sym ? K_X3_SYM : K_X3;
-    // executed MFMA flops: 3 products of 2 * tile^3 per tile-step
-    pe.flops = 3.0 * 2.0 * (double)num_tiles(np, np, sym) * kTile * kTile * (double)np;
+    // executed MFMA flops: 3 products of 2 * tile^2 * K per launched tile
+    const double t = (double)x3_tile(np, np, sym);
+    pe.flops = 3.0 * 2.0 * (double)x3_blocks(np, np, sym) * t * t * (double)np;
     HIP_TRY(hipEventRecord(pe.a, st));
   }
   HIP_TRY(launch_gemm_x3(Ah, Al, np, Bh, Bl, np, np, np, np, sym, ep, st));
@@ -281,9 +286,8 @@ static void series(int m, double* c) {
   for (int k = 1; k <= m; ++k) c[k] = c[k - 1] * (2.0 * k - 1.0) / (2.0 * k);
 }
 
-// Frobenius norm of the last GEMM2's partials -> host
-static int fetch_err(Ctx& c, double* err) {
-  const int count = num_tiles(c.np, c.np, true);
+// Frobenius norm from the partials of the last GEMM2 (count = its block count) -> host
+static int fetch_err(Ctx& c, int count, double* err) {
   HIP_TRY(launch_norm_finalize(c.w->partials, count, c.w->err_dev, c.st));
   HIP_TRY(hipMemcpyAsync(c.w->host_err, c.w->err_dev, sizeof(double), hipMemcpyDeviceToHost, c.st));
   HIP_TRY(hipStreamSynchronize(c.st));
@@ -322,7 +326,7 @@ static int delta_eval(Ctx& c, bool high, bool want_split, int cur, double* err) 
     e2.partials = w.partials;
     ZF_TRY(gemm_f64(w.z64c[cur], w.a64t, np, true, e2, c.st));
   }
-  return fetch_err(c, err);
+  return fetch_err(c, high ? num_tiles(np, np, true) : x3_blocks(np, np, true), err);
 }
 
 // Q = sum_{k=1..m} c_k delta^k by Horner over symmetric GEMMs (m >= 2).
@@ -456,7 +460,7 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   const bool mixed = o.precision != ZF_FP64;
   const bool use_h = !mixed || o.refine != ZF_REFINE_OFF;
   const bool x3corr = mixed && o.refine == ZF_REFINE_F64_DELTA;
-  const int np = round_up(n, kTile);
+  const int np = pad_order(n);
   Workspace* w = nullptr;
   ZF_TRY(ws_get(np, mixed, use_h, &w));
 
@@ -578,7 +582,7 @@ int zf_residual(const double* S, const double* Z, int n, double* err_f, void* st
   if (!S || !Z || !err_f) return fail(ZF_ERR_ARG, "NULL argument");
   if (n <= 0) return fail(ZF_ERR_ARG, "n must be >= 1 (got %d)", n);
   hipStream_t st = (hipStream_t)stream;
-  const int np = round_up(n, kTile);
+  const int np = pad_order(n);
   Workspace* w = nullptr;
   ZF_TRY(ws_get(np, false, true, &w));
   Ctx c;
@@ -658,7 +662,7 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
   // pad every operand to a common square tile multiple
   int np = m > nn ? m : nn;
   if (k > np) np = k;
-  np = round_up(np, kTile);
+  np = round_up(np, 256);
   const size_t e = (size_t)np * np;
   std::vector<void*> tmp;
   auto alloc = [&](size_t bytes, void** p) -> int {
@@ -719,7 +723,7 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
       cleanup();
       return rc;
     }
-    he = launch_norm_finalize(part, num_tiles(np, np, sym != 0), nrm, st);
+    he = launch_norm_finalize(part, precision == ZF_BF16X3 ? x3_blocks(np, np, sym != 0) : num_tiles(np, np, sym != 0), nrm, st);
   }
   if (he == hipSuccess)
     he = hipMemcpy2DAsync(C, (size_t)nn * 8, c64, (size_t)np * 8, (size_t)nn * 8, m,

@@ -73,7 +73,9 @@ struct EpiParams {
 // Launchers (return hipSuccess or the launch error).  All dimensions must be
 // multiples of kTile; the caller pads.  Symmetric mode requires M == N.
 constexpr int kTile = 128;
-int num_tiles(int M, int N, bool sym);
+int num_tiles(int M, int N, bool sym);   // blocks of the FP64 kernel (kTile tiles)
+int x3_tile(int M, int N, bool sym);     // tile edge the BF16x3 launch will use
+int x3_blocks(int M, int N, bool sym);   // blocks (= norm partials) of that launch
 
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,

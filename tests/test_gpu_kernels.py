@@ -83,8 +83,10 @@ def test_gemm_f64(zf, m, nn, k):
     assert np.all(np.abs(C.cpu().numpy() - ref) <= bound)
 
 
+@pytest.mark.parametrize("tile", ["128", "256"])
 @pytest.mark.parametrize("m,nn,k", SHAPES)
-def test_gemm_bf16x3(zf, m, nn, k):
+def test_gemm_bf16x3(zf, m, nn, k, tile, monkeypatch):
+    monkeypatch.setenv("ZF_X3_TILE", tile)
     rng = np.random.default_rng(m * 5 + nn + 3 * k)
     A = rng.standard_normal((m, k)) * np.exp(rng.uniform(-3, 3, (m, 1)))
     B = rng.standard_normal((nn, k))
@@ -100,9 +102,9 @@ def test_gemm_bf16x3(zf, m, nn, k):
     assert np.all(np.abs(C - exact) <= (3 * u * u + 3 * k * U32) * (np.abs(A) @ np.abs(B).T) * 1.01)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
-@pytest.mark.parametrize("n,k", [(128, 128), (300, 200), (640, 512), (129, 64)])
-def test_gemm_symmetric_delta_epilogue(zf, prec, n, k):
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "bf16x3-t128"])
+@pytest.mark.parametrize("n,k", [(128, 128), (300, 200), (640, 512), (129, 64), (1000, 256)])
+def test_gemm_symmetric_delta_epilogue(zf, prec, n, k, monkeypatch):
     """delta = I - A M A^T (symmetric product) in symmetric mode: only tiles on or
     above the diagonal are computed; the result is mirrored exactly and the norm
     partials reproduce ||delta||_F."""
@@ -111,6 +113,9 @@ def test_gemm_symmetric_delta_epilogue(zf, prec, n, k):
     M = rng.standard_normal((k, k))
     M = (M + M.T) / 2
     B = A @ M                     # A B^T = A M A^T is symmetric
+    if prec.endswith("-t128"):
+        monkeypatch.setenv("ZF_X3_SYM_TILE", "128")
+        prec = prec[:-5]
     C, nsq = zf.t_gemm(prec, _cuda(A), _cuda(B), sym=True, beta=-1.0, gamma=1.0)
     C = C.cpu().numpy()
     assert np.array_equal(C, C.T)
