@@ -26,6 +26,20 @@
 
 namespace zf {
 
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// 16 bytes per lane, global -> LDS, bypassing VGPRs: lane l's data lands at
+// lds_dst + 16 l (lds_dst is wave-uniform, passed in M0).  Issued as inline asm so
+// that the compiler does not serialize it against reads of the other pipeline
+// stage; callers wait with s_waitcnt vmcnt(0) before the barrier that publishes it.
+__device__ __forceinline__ void dma16(const u16* gsrc, u16* lds_dst) {
+  const unsigned m0v = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lds_ptr)lds_dst);
+  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+               :
+               : "s"(m0v), "v"(gsrc)
+               : "memory", "m0");
+}
+
 // ---------------------------------------------------------------------------
 // tile index -> (tile_row, tile_col)
 // ---------------------------------------------------------------------------
@@ -199,7 +213,8 @@ struct X3Cfg {
   static constexpr int A_PT = BM * VPR / NT, B_PT = BN * VPR / NT;
   static constexpr int STAGE = (BM + BN) * 2 * BK;  // 16-bit elements per pipeline stage
   static constexpr int SP = BN + 1;                  // epilogue strip pitch (floats)
-  static constexpr int LDS_BYTES = (2 * STAGE * 2 > WTM * SP * 4) ? 2 * STAGE * 2 : WTM * SP * 4;
+  // a stage buffer also holds one 32-row epilogue strip
+  static constexpr int STAGE_ELEMS = (STAGE > 32 * SP * 2) ? STAGE : 32 * SP * 2;
   static_assert(BK == 32, "the LDS swizzle assumes 64-byte tile rows");
   static_assert(BM % (WM * 32) == 0 && BN % (WN * 32) == 0, "wave tile");
   static_assert((BM * VPR) % NT == 0 && (BN * VPR) % NT == 0, "load split");
@@ -219,7 +234,7 @@ __global__ void __launch_bounds__(WM* WN * 64)
                    const u16* __restrict__ Bhi, const u16* __restrict__ Blo, int ldb, int K,
                    int tiles_n, int sym, EpiParams ep) {
   using C = X3Cfg<BM, BN, BK, WM, WN>;
-  __shared__ __attribute__((aligned(16))) u16 lds[C::LDS_BYTES / 2];
+  __shared__ __attribute__((aligned(16))) u16 lds[2 * C::STAGE_ELEMS];
   __shared__ double red[C::NT / 64];
 
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -229,21 +244,25 @@ __global__ void __launch_bounds__(WM* WN * 64)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
 
-  // Global -> register -> LDS staging, one K block ahead.  Written as plain
-  // unrolled loops over constant indices so the staging arrays stay in VGPRs.
-  uint4 pa_h[C::A_PT], pa_l[C::A_PT], pb_h[C::B_PT], pb_l[C::B_PT];
-  int a_off[C::A_PT], b_off[C::B_PT], a_lds[C::A_PT], b_lds[C::B_PT];
+  // Operands go global -> LDS directly (global_load_lds_dwordx4), one K block
+  // ahead, into the swizzled layout: a wave's 64 lanes fill one contiguous 1 KB
+  // block (16 rows x 4 physical chunks), so lane l loads row 16 j + l / 4, logical
+  // chunk (l % 4) ^ f(row), which is exactly where the reader looks for it.
+  constexpr int NW = WM * WN;
+  constexpr int ABL = BM / 16 / NW, BBL = BN / 16 / NW;  // 1 KB blocks per wave and matrix
+  static_assert(ABL * 16 * NW == BM && BBL * 16 * NW == BN, "direct-load split");
+  int a_goff[ABL], b_goff[BBL];
 #pragma unroll
-  for (int i = 0; i < C::A_PT; ++i) {
-    const int v = tid + i * C::NT, r = v / C::VPR, c = v % C::VPR;
-    a_off[i] = (m0 + r) * lda + c * 8;
-    a_lds[i] = swz64(r, c);
+  for (int i = 0; i < ABL; ++i) {
+    const int r = 16 * (wave + i * NW) + (lane >> 2);
+    const int c = (lane & 3) ^ (((r >> 1) ^ (r >> 3)) & 3);
+    a_goff[i] = (m0 + r) * lda + c * 8;
   }
 #pragma unroll
-  for (int i = 0; i < C::B_PT; ++i) {
-    const int v = tid + i * C::NT, r = v / C::VPR, c = v % C::VPR;
-    b_off[i] = (n0 + r) * ldb + c * 8;
-    b_lds[i] = swz64(r, c);
+  for (int i = 0; i < BBL; ++i) {
+    const int r = 16 * (wave + i * NW) + (lane >> 2);
+    const int c = (lane & 3) ^ (((r >> 1) ^ (r >> 3)) & 3);
+    b_goff[i] = (n0 + r) * ldb + c * 8;
   }
 
   f32x16 acc[C::FM][C::FN];
@@ -253,129 +272,107 @@ __global__ void __launch_bounds__(WM* WN * 64)
     for (int b = 0; b < C::FN; ++b) acc[a][b] = f32x16{};
 
   const int KT = K / BK;
-#pragma unroll
-  for (int i = 0; i < C::A_PT; ++i) {
-    pa_h[i] = *reinterpret_cast<const uint4*>(Ahi + a_off[i]);
-    pa_l[i] = *reinterpret_cast<const uint4*>(Alo + a_off[i]);
-  }
-#pragma unroll
-  for (int i = 0; i < C::B_PT; ++i) {
-    pb_h[i] = *reinterpret_cast<const uint4*>(Bhi + b_off[i]);
-    pb_l[i] = *reinterpret_cast<const uint4*>(Blo + b_off[i]);
-  }
-#pragma unroll
-  for (int i = 0; i < C::A_PT; ++i) {
-    *reinterpret_cast<uint4*>(lds + a_lds[i]) = pa_h[i];
-    *reinterpret_cast<uint4*>(lds + BM * BK + a_lds[i]) = pa_l[i];
-  }
-#pragma unroll
-  for (int i = 0; i < C::B_PT; ++i) {
-    *reinterpret_cast<uint4*>(lds + 2 * BM * BK + b_lds[i]) = pb_h[i];
-    *reinterpret_cast<uint4*>(lds + 2 * BM * BK + BN * BK + b_lds[i]) = pb_l[i];
-  }
-  __syncthreads();
+#define ZF_X3_ISSUE(buf, k0)                                                                      \
+  do {                                                                                            \
+    u16* base_ = (buf);                                                                           \
+    _Pragma("unroll") for (int i = 0; i < ABL; ++i) {                                             \
+      const int j = wave + i * NW;                                                                \
+      dma16(Ahi + a_goff[i] + (k0), base_ + j * 512);                                             \
+      dma16(Alo + a_goff[i] + (k0), base_ + BM * BK + j * 512);                                   \
+    }                                                                                             \
+    _Pragma("unroll") for (int i = 0; i < BBL; ++i) {                                             \
+      const int j = wave + i * NW;                                                                \
+      dma16(Bhi + b_goff[i] + (k0), base_ + 2 * BM * BK + j * 512);                               \
+      dma16(Blo + b_goff[i] + (k0), base_ + 2 * BM * BK + BN * BK + j * 512);                     \
+    }                                                                                             \
+  } while (0)
 
+  // Fragment reads of one stage and the three MFMA passes of its K block.
+  // Fragments are read per product pass (hh, hl, lh) so that only three of the
+  // four operand halves are live at once; consecutive MFMAs never update the
+  // same accumulator.
+#define ZF_X3_COMPUTE(buf)                                                                        \
+  do {                                                                                            \
+    const u16* as_h = (buf);                                                                      \
+    const u16* as_l = as_h + BM * BK;                                                             \
+    const u16* bs_h = as_l + BM * BK;                                                             \
+    const u16* bs_l = bs_h + BN * BK;                                                             \
+    _Pragma("unroll") for (int kk = 0; kk < BK / 16; ++kk) {                                      \
+      const int ch = kk * 2 + (lane >> 5);                                                        \
+      int ao[C::FM], bo[C::FN];                                                                   \
+      _Pragma("unroll") for (int a = 0; a < C::FM; ++a)                                           \
+          ao[a] = swz64(wm * C::WTM + a * 32 + (lane & 31), ch);                                  \
+      _Pragma("unroll") for (int b = 0; b < C::FN; ++b)                                           \
+          bo[b] = swz64(wn * C::WTN + b * 32 + (lane & 31), ch);                                  \
+      bf16x8 ah[C::FM], bx[C::FN], bl[C::FN];                                                     \
+      _Pragma("unroll") for (int a = 0; a < C::FM; ++a)                                           \
+          ah[a] = *reinterpret_cast<const bf16x8*>(as_h + ao[a]);                                 \
+      _Pragma("unroll") for (int b = 0; b < C::FN; ++b)                                           \
+          bx[b] = *reinterpret_cast<const bf16x8*>(bs_h + bo[b]);                                 \
+      _Pragma("unroll") for (int a = 0; a < C::FM; ++a)                                           \
+      _Pragma("unroll") for (int b = 0; b < C::FN; ++b)                                           \
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bx[b], acc[a][b], 0, 0, 0);  \
+      _Pragma("unroll") for (int b = 0; b < C::FN; ++b)                                           \
+          bl[b] = *reinterpret_cast<const bf16x8*>(bs_l + bo[b]);                                 \
+      _Pragma("unroll") for (int a = 0; a < C::FM; ++a)                                           \
+      _Pragma("unroll") for (int b = 0; b < C::FN; ++b)                                           \
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);  \
+      _Pragma("unroll") for (int a = 0; a < C::FM; ++a)                                           \
+          ah[a] = *reinterpret_cast<const bf16x8*>(as_l + ao[a]);                                 \
+      _Pragma("unroll") for (int a = 0; a < C::FM; ++a)                                           \
+      _Pragma("unroll") for (int b = 0; b < C::FN; ++b)                                           \
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bx[b], acc[a][b], 0, 0, 0);  \
+    }                                                                                             \
+  } while (0)
+
+  ZF_X3_ISSUE(lds, 0);
+  __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's direct loads have landed
+  __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
-    const int s = kt & 1;
-    // next K block; the last iteration re-reads its own block into the idle stage
-    const int kn = (kt + 1 < KT ? kt + 1 : kt) * BK;
-#pragma unroll
-    for (int i = 0; i < C::A_PT; ++i) {
-      pa_h[i] = *reinterpret_cast<const uint4*>(Ahi + a_off[i] + kn);
-      pa_l[i] = *reinterpret_cast<const uint4*>(Alo + a_off[i] + kn);
-    }
-#pragma unroll
-    for (int i = 0; i < C::B_PT; ++i) {
-      pb_h[i] = *reinterpret_cast<const uint4*>(Bhi + b_off[i] + kn);
-      pb_l[i] = *reinterpret_cast<const uint4*>(Blo + b_off[i] + kn);
-    }
-    const u16* as_h = lds + s * C::STAGE;
-    const u16* as_l = as_h + BM * BK;
-    const u16* bs_h = as_l + BM * BK;
-    const u16* bs_l = bs_h + BN * BK;
-#pragma unroll
-    for (int kk = 0; kk < BK / 16; ++kk) {
-      const int ch = kk * 2 + (lane >> 5);  // logical 16-byte chunk of this lane's 8 K values
-      // Fragments are read per product pass (hh, hl, lh) so that only three of
-      // the four operand halves are live at once; consecutive MFMAs never
-      // update the same accumulator.
-      int ao[C::FM], bo[C::FN];
-#pragma unroll
-      for (int a = 0; a < C::FM; ++a) ao[a] = swz64(wm * C::WTM + a * 32 + (lane & 31), ch);
-#pragma unroll
-      for (int b = 0; b < C::FN; ++b) bo[b] = swz64(wn * C::WTN + b * 32 + (lane & 31), ch);
-      bf16x8 ah[C::FM], bx[C::FN];
-#pragma unroll
-      for (int a = 0; a < C::FM; ++a) ah[a] = *reinterpret_cast<const bf16x8*>(as_h + ao[a]);
-#pragma unroll
-      for (int b = 0; b < C::FN; ++b) bx[b] = *reinterpret_cast<const bf16x8*>(bs_h + bo[b]);
-#pragma unroll
-      for (int a = 0; a < C::FM; ++a)
-#pragma unroll
-        for (int b = 0; b < C::FN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bx[b], acc[a][b], 0, 0, 0);
-      bf16x8 bl[C::FN];
-#pragma unroll
-      for (int b = 0; b < C::FN; ++b) bl[b] = *reinterpret_cast<const bf16x8*>(bs_l + bo[b]);
-#pragma unroll
-      for (int a = 0; a < C::FM; ++a)
-#pragma unroll
-        for (int b = 0; b < C::FN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-#pragma unroll
-      for (int a = 0; a < C::FM; ++a) ah[a] = *reinterpret_cast<const bf16x8*>(as_l + ao[a]);
-#pragma unroll
-      for (int a = 0; a < C::FM; ++a)
-#pragma unroll
-        for (int b = 0; b < C::FN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bx[b], acc[a][b], 0, 0, 0);
-    }
-    u16* ns = lds + (s ^ 1) * C::STAGE;
-#pragma unroll
-    for (int i = 0; i < C::A_PT; ++i) {
-      *reinterpret_cast<uint4*>(ns + a_lds[i]) = pa_h[i];
-      *reinterpret_cast<uint4*>(ns + BM * BK + a_lds[i]) = pa_l[i];
-    }
-#pragma unroll
-    for (int i = 0; i < C::B_PT; ++i) {
-      *reinterpret_cast<uint4*>(ns + 2 * BM * BK + b_lds[i]) = pb_h[i];
-      *reinterpret_cast<uint4*>(ns + 2 * BM * BK + BN * BK + b_lds[i]) = pb_l[i];
-    }
+    u16* cur = lds + (kt & 1) * C::STAGE_ELEMS;
+    u16* nxt = lds + ((kt & 1) ^ 1) * C::STAGE_ELEMS;
+    // nxt was last read in iteration kt - 1, which every wave has left
+    if (kt + 1 < KT) ZF_X3_ISSUE(nxt, (kt + 1) * BK);
+    ZF_X3_COMPUTE(cur);
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
     __syncthreads();
   }
+#undef ZF_X3_ISSUE
+#undef ZF_X3_COMPUTE
 
-  // Epilogue through LDS, one wave row (WTM x BN strip) at a time.  A lane holds
+  // Epilogue through LDS, one 32-row strip of the tile at a time.  A lane holds
   // rows 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32 of each 32x32 block;
-  // the strip is then walked row-major (normal outputs, coalesced) and
-  // column-major (transposed / mirrored outputs, coalesced).
+  // the strip is walked row-major (normal outputs, coalesced) and column-major
+  // (transposed / mirrored outputs, coalesced).
   const int mode = sym ? (ti == tj ? 2 : 1) : 0;
   const bool any_t = ep.ot64 || ep.ot32 || ep.othi;
   float* strip = reinterpret_cast<float*>(lds);
   double nsum = 0.0;
   for (int wr = 0; wr < WM; ++wr) {
-    __syncthreads();
-    if (wm == wr) {
 #pragma unroll
-      for (int a = 0; a < C::FM; ++a)
+    for (int a = 0; a < C::FM; ++a) {
+      __syncthreads();
+      if (wm == wr) {
 #pragma unroll
         for (int b = 0; b < C::FN; ++b)
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
-            const int lr = a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int lr = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
             const int lc = wn * C::WTN + b * 32 + (lane & 31);
             strip[lr * C::SP + lc] = acc[a][b][r];
           }
-    }
-    __syncthreads();
-    const int row0 = m0 + wr * C::WTM;
-    for (int e = tid; e < C::WTM * BN; e += C::NT) {
-      const int lr = e / BN, lc = e % BN;
-      epi_elem(ep, row0 + lr, n0 + lc, strip[lr * C::SP + lc], mode, 1, nsum);
-    }
-    if (any_t) {
-      for (int e = tid; e < C::WTM * BN; e += C::NT) {
-        const int lr = e % C::WTM, lc = e / C::WTM;
-        epi_elem(ep, row0 + lr, n0 + lc, strip[lr * C::SP + lc], mode, 0, nsum);
+      }
+      __syncthreads();
+      const int row0 = m0 + wr * C::WTM + a * 32;
+      for (int e = tid; e < 32 * BN; e += C::NT) {
+        const int lr = e / BN, lc = e % BN;
+        epi_elem(ep, row0 + lr, n0 + lc, strip[lr * C::SP + lc], mode, 1, nsum);
+      }
+      if (any_t) {
+        for (int e = tid; e < 32 * BN; e += C::NT) {
+          const int lr = e & 31, lc = e >> 5;
+          epi_elem(ep, row0 + lr, n0 + lc, strip[lr * C::SP + lc], mode, 0, nsum);
+        }
       }
     }
   }
