@@ -43,6 +43,7 @@ extern "C" {
 #define ZF_OK 0
 /* warnings (bitmask, positive) */
 #define ZF_WARN_MAXSWEEPS 1   /* a phase ended at its sweep cap, not at the stop test */
+#define ZF_WARN_Z0_FALLBACK 2 /* the learned guess was unavailable or rejected: scaled identity */
 #define ZF_WARN_HIST_TRUNC 4  /* more residuals than hist_cap; the rest were dropped */
 /* errors (negative) */
 #define ZF_ERR_ARG -1            /* invalid argument (n <= 0, order out of range, NULL, ...) */
@@ -79,6 +80,8 @@ typedef struct {
   int max_sweeps; /* cap on Z updates in the first phase; <= 0 means 100                */
   int refine;     /* enum zf_refine_mode; ignored for ZF_FP64                            */
   int max_refine; /* cap on Z updates in the refinement phase; <= 0 means 10             */
+  int z0;         /* guess when Z0 is NULL: 0 scaled identity, 1 learned (zf_mlp_*) with the
+                     scaled identity as fallback                                          */
 } zf_opts;
 
 typedef struct {
@@ -90,10 +93,12 @@ typedef struct {
   double final_err;/* ||I - Z^T S Z||_F of the returned Z as last evaluated (FP64 when a
                       FP64 evaluation ran, else the low-precision value)               */
   double final_rms;/* final_err / sqrt(n)                                              */
+  int status;      /* 0, or the ZF_ERR_* code of this matrix (batched calls report each)  */
+  int z0_used;     /* 0 given, 1 scaled identity, 2 learned                               */
 } zf_result;
 
 /* Fill *opts with the defaults: order 2, ZF_BF16X3, ZF_STOP_RATIO, 100 sweeps,
- * ZF_REFINE_F64_DELTA, 10 refinement sweeps. */
+ * ZF_REFINE_F64_DELTA, 10 refinement sweeps, scaled-identity guess. */
 void zf_default_opts(zf_opts* opts);
 
 /*
@@ -119,6 +124,77 @@ int zf_refine(const double* S, const double* Z0, int n, int order, int precision
  * record (res may be NULL). */
 int zf_refine_ex(const double* S, const double* Z0, int n, const zf_opts* opts, double* Z,
                  zf_result* res, double* hist, int hist_cap, void* stream);
+
+/*
+ * zf_refine_batched -- refine count independent matrices of uneven order together.
+ *   S[m], Z[m]  device pointers (host arrays of count pointers), n[m] x n[m] FP64, n[m] in
+ *               1..8192; Z0 may be NULL (all scaled identity) or hold NULL entries.
+ *   opts        order must be 2, precision ZF_BF16X3, refine ZF_REFINE_OFF or
+ *               ZF_REFINE_F64_DELTA (opts NULL = defaults).
+ *   res         host[count] or NULL: per-matrix result including status.
+ *   hist        host[count * hist_cap]: matrix m's residual history at m * hist_cap.
+ * Every matrix runs the recursion and stop test of zf_refine_ex; the matrices advance
+ * in lockstep macro-sweeps of grouped matrix-core GEMMs (one persistent launch per
+ * stage), replayed as a HIP graph, with the stop state kept on the device.  The
+ * tile edge per matrix comes from the table of zf_batched_set_tiles /
+ * zf_batched_autotune.  Returns the OR of the warnings, or the first failing
+ * matrix's error (every result is still filled).  Synchronizes the stream.
+ */
+int zf_refine_batched(int count, const double* const* S, const double* const* Z0, const int* n,
+                      const zf_opts* opts, double* const* Z, zf_result* res, double* hist,
+                      int hist_cap, void* stream);
+
+/* zf_batched_set_tiles -- tile table: orders n <= max_n[k] use tile[k] (64 or 128); the
+ * last entry covers every larger order.  1 <= count <= 16. */
+int zf_batched_set_tiles(const int* max_n, const int* tile, int count);
+
+/* zf_batched_get_tiles -- copy the table out (cap entries); returns its length. */
+int zf_batched_get_tiles(int* max_n, int* tile, int cap);
+
+/* zf_batched_autotune -- for each bucket order bucket_n[b], time the grouped BF16x3
+ * residual GEMMs of batch matrices with 64 and 128 tiles (reps repetitions), store the
+ * faster edge in best_tile[b] and the times in ms[2 b], ms[2 b + 1] (ms may be NULL),
+ * and install the table (bucket b covers orders up to bucket_n[b]). */
+int zf_batched_autotune(const int* bucket_n, int nbuckets, int batch, int reps, int* best_tile,
+                        double* ms, void* stream);
+
+/* zf_batched_use_graph -- 1 (default): replay the captured macro-sweep graph; 0: launch
+ * the same kernels eagerly (for checking the graph). */
+void zf_batched_use_graph(int on);
+
+/* zf_batched_release -- free the batched path's cached arena, graph and stream. */
+void zf_batched_release(void);
+
+/*
+ * Learned initial guess Z0 = (c0 I + c1 S/g + c2 (S/g)^2) / sqrt(g), g = max_i sum_j |S_ij|.
+ * The recursion converges from any Z0 with ||Z0^T S Z0 - I||_2 < 1 (Sec. III); good guesses
+ * save sweeps (Sec. VI).  Features (8 floats): log N, tr((S/g)^k)/N for k = 1..4,
+ * max(g_lo,0)/g, g_lo/g, mean_i sum_j |S_ij| / g, with g_lo the Gershgorin lower bound.
+ * Network: 8 -> 64 -> 64 -> 3, tanh, FP32, 4931 parameters in the order W1 (64x8), b1,
+ * W2 (64x64), b2, W3 (3x64), b3; inputs and outputs standardized by zf_mlp_set_norm.
+ * With opts.z0 = 1 and Z0 == NULL, zf_refine_ex predicts (c0, c1, c2), rescales them so
+ * that max x p(x)^2 <= 1.9 on the Gershgorin interval [max(g_lo,0)/g, 1], and falls back
+ * to the scaled identity (ZF_WARN_Z0_FALLBACK) if p <= 0 there or no network is loaded.
+ */
+/* zf_features -- the 8 features of device S (n x n) into device feats (8 floats). */
+int zf_features(const double* S, int n, float* feats, void* stream);
+/* zf_guess_label -- training label: c (host, 3 doubles) minimizing
+ * ||S^(1/2) (p(S/g)/sqrt(g) - Z)||_F for device S, Z (n x n), by FP64 GEMMs. */
+int zf_guess_label(const double* S, const double* Z, int n, double* c, void* stream);
+int zf_mlp_set_params(const float* host_params, int count);  /* count must be 4931 */
+int zf_mlp_get_params(float* host_params, int count);
+/* standardization: x' = (x - mu_x) / sd_x (8 each), y = y' sd_y + mu_y (3 each) */
+int zf_mlp_set_norm(const float* mu_x, const float* sd_x, const float* mu_y, const float* sd_y);
+/* one Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error of the standardized
+ * labels; feats (batch x 8) and labels (batch x 3, raw c) are device FP32; loss (host) may
+ * be NULL (then the call does not synchronize). */
+int zf_mlp_train_step(const float* feats, const float* labels, int batch, float lr, float* loss,
+                      void* stream);
+/* gradient of that loss (host, 4931 floats) and the loss, without updating (for checks) */
+int zf_mlp_grad(const float* feats, const float* labels, int batch, float* grad_host,
+                float* loss_host, void* stream);
+/* raw coefficients (host, 3 doubles) predicted for one device feature vector */
+int zf_mlp_predict(const float* feats, double* coef_host, void* stream);
 
 /* zf_residual -- err_f = ||Z^T S Z - I||_F evaluated with FP64 products (host double).
  * S, Z: device n x n FP64. */

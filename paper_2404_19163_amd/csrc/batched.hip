@@ -1,0 +1,942 @@
+// Batched refinement: many overlap matrices of uneven order refined together.
+//
+// Every matrix runs the same recursion as zf_refine_ex (Sec. III, Algorithm 2 in
+// the low-precision phase, the FP64 refinement phase of Sec. IV.B), but the
+// matrices advance in lockstep "macro-sweeps".  One macro-sweep is
+//
+//   L1  grouped BF16x3 GEMM  A^T = Z^T S           (matrices in the low phase)
+//   L2  grouped BF16x3 GEMM  delta = I - Z^T A     (symmetric, norm partials)
+//   H1  grouped FP64 GEMM    A^T = Z^T S           (matrices in the FP64 phase)
+//   H2  grouped FP64 GEMM    delta = I - Z^T A     (symmetric, norm partials)
+//   DECIDE  per matrix: Err, history, stop test, next action (device-side)
+//   WIDEN   FP32 -> FP64 Z for matrices that just left the low phase
+//   U3  grouped BF16x3 GEMM  Q = c1 delta + c2 delta^2  (matrices updating)
+//   U4  grouped BF16x3 GEMM  Z_new = Z + Z Q           (matrices updating)
+//
+// Each grouped GEMM is one persistent launch over a static table of (matrix,
+// tile) tasks; a task whose matrix is not in that stage is skipped on the device,
+// so the macro-sweep is a fixed sequence of launches, captured once in a HIP graph
+// and replayed until every matrix is done.  The tile edge of each matrix (64 or
+// 128) comes from a table indexed by its order, filled by zf_batched_autotune or
+// left at its defaults.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "zf.h"
+#include "zf_internal.h"
+#include "gemm_tiles.inc"
+
+namespace zf {
+
+#define BHIP_TRY(expr)                                                                       \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return set_error(ZF_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                       __LINE__);                                                            \
+  } while (0)
+
+enum { PH_LOW = 0, PH_HIGH = 1 };
+enum { ACT_EVAL = 0, ACT_UPDATE = 1, ACT_TRANSITION = 2, ACT_DONE = 3 };
+enum { OP_L1 = 0, OP_L2, OP_H1, OP_H2, OP_U3, OP_U4 };
+
+// Per-matrix record: buffers (carved from one arena) and the device-side state of
+// the recursion.  Only the DECIDE kernel writes the state.
+struct BMat {
+  int n, np, tile, tiles_sym;
+  long long pbase;  // first norm partial of this matrix
+  int phase, action, it, cur, src;
+  int upd_l, upd_h, evals_l, evals_h, flags, status, hist_len;
+  double prev, err_l, err_h;
+  double* hist;
+  u16 *s_hi, *s_lo, *zr_hi[2], *zr_lo[2], *zc_hi[2], *zc_lo[2];
+  u16 *at_hi, *at_lo, *d_hi, *d_lo, *q_hi, *q_lo;
+  float* z32[2];
+  double *s64, *z64r[2], *z64c[2], *a64t, *d64;
+};
+
+struct TileTask {
+  int m;
+  short ti, tj;
+};
+
+// ---------------------------------------------------------------------------
+// grouped GEMMs
+// ---------------------------------------------------------------------------
+using X3_64 = X3Cfg<64, 64, 32, 2, 2>;
+using X3_128 = X3Cfg<128, 128, 32, 2, 2>;
+using F64_64 = F64Cfg<64, 64, 16, 2, 2>;
+using F64_128 = F64Cfg<128, 128, 16, 2, 2>;
+static_assert(X3_64::NT == 256 && X3_128::NT == 256 && F64_64::NT == 256 && F64_128::NT == 256,
+              "grouped kernels run every tile body with one 256-thread block");
+
+__device__ __forceinline__ bool op_applies(int op, int phase, int action) {
+  switch (op) {
+    case OP_L1:
+    case OP_L2:
+      return phase == PH_LOW && action != ACT_DONE;
+    case OP_H1:
+    case OP_H2:
+      return phase == PH_HIGH && action != ACT_DONE;
+    default:
+      return action == ACT_UPDATE;
+  }
+}
+
+__global__ void __launch_bounds__(256, 2)
+    grouped_x3_kernel(const TileTask* __restrict__ tasks, int ntasks, const BMat* __restrict__ mats,
+                      int op, double c1, double c2, double* partials) {
+  __shared__ __attribute__((aligned(16))) u16 lds[2 * X3_128::STAGE_ELEMS];
+  __shared__ double red[4];
+  for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+    const TileTask tk = tasks[t];
+    const BMat& M = mats[tk.m];
+    if (!op_applies(op, M.phase, M.action)) continue;
+    const int np = M.np, T = M.tile;
+    EpiParams ep;
+    memset(&ep, 0, sizeof ep);
+    ep.beta = 1.0;
+    ep.ld = np;
+    ep.n_valid = M.n;
+    const u16 *ah, *al, *bh, *bl;
+    int mode = 0, pidx = 0;
+    if (op == OP_L1) {
+      ah = M.zc_hi[M.cur];
+      al = M.zc_lo[M.cur];
+      bh = M.s_hi;
+      bl = M.s_lo;
+      ep.ohi = M.at_hi;
+      ep.olo = M.at_lo;
+    } else if (op == OP_L2) {
+      ah = M.zc_hi[M.cur];
+      al = M.zc_lo[M.cur];
+      bh = M.at_hi;
+      bl = M.at_lo;
+      ep.beta = -1.0;
+      ep.gamma = 1.0;
+      ep.ohi = ep.othi = M.d_hi;
+      ep.olo = ep.otlo = M.d_lo;
+      ep.partials = partials + M.pbase;
+    } else if (op == OP_U3) {
+      ah = bh = M.d_hi;
+      al = bl = M.d_lo;
+      ep.alpha = c1;
+      ep.beta = c2;
+      if (M.phase == PH_HIGH) ep.d64 = M.d64;
+      else {
+        ep.dhi = M.d_hi;
+        ep.dlo = M.d_lo;
+      }
+      ep.ohi = ep.othi = M.q_hi;
+      ep.olo = ep.otlo = M.q_lo;
+    } else {  // OP_U4: Z[cur] = Z[src] + Z[src] Q
+      ah = M.zr_hi[M.src];
+      al = M.zr_lo[M.src];
+      bh = M.q_hi;
+      bl = M.q_lo;
+      ep.alpha = 1.0;
+      ep.ohi = M.zr_hi[M.cur];
+      ep.olo = M.zr_lo[M.cur];
+      if (M.phase == PH_HIGH) {
+        ep.d64 = M.z64r[M.src];
+        ep.o64 = M.z64r[M.cur];
+        ep.ot64 = M.z64c[M.cur];
+      } else {
+        ep.d32 = M.z32[M.src];
+        ep.o32 = M.z32[M.cur];
+        ep.othi = M.zc_hi[M.cur];
+        ep.otlo = M.zc_lo[M.cur];
+      }
+    }
+    const bool sym = (op == OP_L2 || op == OP_U3);
+    if (sym) {
+      mode = (tk.ti == tk.tj) ? 2 : 1;
+      // index of (ti, tj) in the row-major upper triangle of a T x T tile grid
+      const int tiles = np / T;
+      pidx = tk.ti * tiles - tk.ti * (tk.ti - 1) / 2 + (tk.tj - tk.ti);
+    }
+    if (T == 64)
+      x3_tile<64, 64, 32, 2, 2>(ah, al, np, bh, bl, np, np, tk.ti * 64, tk.tj * 64, mode, ep, pidx,
+                                lds, red);
+    else
+      x3_tile<128, 128, 32, 2, 2>(ah, al, np, bh, bl, np, np, tk.ti * 128, tk.tj * 128, mode, ep,
+                                  pidx, lds, red);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256, 2)
+    grouped_f64_kernel(const TileTask* __restrict__ tasks, int ntasks, const BMat* __restrict__ mats,
+                       int op, double* partials) {
+  __shared__ double lds[2 * F64_128::STAGE];
+  __shared__ double red[4];
+  for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+    const TileTask tk = tasks[t];
+    const BMat& M = mats[tk.m];
+    if (!op_applies(op, M.phase, M.action)) continue;
+    const int np = M.np, T = M.tile;
+    EpiParams ep;
+    memset(&ep, 0, sizeof ep);
+    ep.beta = 1.0;
+    ep.ld = np;
+    ep.n_valid = M.n;
+    const double *a, *b;
+    int mode = 0, pidx = 0;
+    if (op == OP_H1) {
+      a = M.z64c[M.cur];
+      b = M.s64;
+      ep.o64 = M.a64t;
+    } else {  // OP_H2
+      a = M.z64c[M.cur];
+      b = M.a64t;
+      ep.beta = -1.0;
+      ep.gamma = 1.0;
+      ep.o64 = ep.ot64 = M.d64;
+      ep.ohi = ep.othi = M.d_hi;
+      ep.olo = ep.otlo = M.d_lo;
+      ep.partials = partials + M.pbase;
+      mode = (tk.ti == tk.tj) ? 2 : 1;
+      const int tiles = np / T;
+      pidx = tk.ti * tiles - tk.ti * (tk.ti - 1) / 2 + (tk.tj - tk.ti);
+    }
+    if (T == 64)
+      f64_tile<64, 64, 16, 2, 2>(a, np, b, np, np, tk.ti * 64, tk.tj * 64, mode, ep, pidx, lds, red);
+    else
+      f64_tile<128, 128, 16, 2, 2>(a, np, b, np, np, tk.ti * 128, tk.tj * 128, mode, ep, pidx, lds,
+                                   red);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// device-side stop test (Algorithm 2, Sec. IV.A) and phase changes
+// ---------------------------------------------------------------------------
+__global__ void decide_kernel(BMat* mats, int count, const double* __restrict__ partials, int order,
+                              int rule, int max_l, int max_h, int refine_on, int hist_cap,
+                              int* remaining) {
+  __shared__ int live;
+  if (threadIdx.x == 0) live = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    BMat& M = mats[i];
+    if (M.action == ACT_DONE) continue;
+    // every matrix not yet done was evaluated in this macro-sweep
+    double s = 0.0;
+    for (int t = 0; t < M.tiles_sym; ++t) s += partials[M.pbase + t];
+    const double err = sqrt(s);
+    if (M.hist_len < hist_cap) M.hist[M.hist_len] = err;
+    M.hist_len++;
+    if (M.phase == PH_LOW) M.evals_l++;
+    else M.evals_h++;
+    if (!isfinite(err)) {
+      M.status = ZF_ERR_NONFINITE;
+      M.action = ACT_DONE;
+      continue;
+    }
+    const int it = M.it;
+    bool stop = false;
+    if (it > 0) stop = (rule == ZF_STOP_MONOTONE) ? (err >= M.prev) : (err > pow(M.prev, (double)(order + 1)));
+    const int cap = (M.phase == PH_LOW) ? max_l : max_h;
+    bool finish = false;
+    int upd = it;
+    double chosen = err;
+    if (stop) {
+      finish = true;
+      if (err > M.prev) {  // the previous iterate is still in the other buffer
+        M.cur ^= 1;
+        upd = it - 1;
+        chosen = M.prev;
+      }
+    } else if (it >= cap) {
+      finish = true;
+      M.flags |= ZF_WARN_MAXSWEEPS;
+    }
+    if (finish) {
+      if (M.phase == PH_LOW) {
+        M.upd_l = upd;
+        M.err_l = chosen;
+        if (refine_on) {
+          M.phase = PH_HIGH;
+          M.it = 0;
+          M.action = ACT_TRANSITION;
+        } else {
+          M.action = ACT_DONE;
+        }
+      } else {
+        M.upd_h = upd;
+        M.err_h = chosen;
+        M.action = ACT_DONE;
+      }
+    } else {
+      M.prev = err;
+      M.it = it + 1;
+      M.src = M.cur;
+      M.cur ^= 1;
+      M.action = ACT_UPDATE;
+    }
+    if (M.action != ACT_DONE) atomicAdd(&live, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) remaining[0] = live;
+}
+
+// ---------------------------------------------------------------------------
+// element-wise batched kernels: a flat index over sum_m rows_m * cols_m, the matrix
+// found by binary search over the prefix offsets
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_matrix(const long long* __restrict__ off, int count, long long e) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// S_m (n x n) -> BF16 pair and (optionally) FP64 copy, zero-padded to np x np
+__global__ void b_split_kernel(const BMat* __restrict__ mats, int count, const double* const* S,
+                               const long long* __restrict__ off, long long total, int with64) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int m = find_matrix(off, count, e);
+    const BMat& M = mats[m];
+    const long long le = e - off[m];
+    const int i = (int)(le / M.np), j = (int)(le % M.np);
+    const double a = (i < M.n && j < M.n) ? S[m][(size_t)i * M.n + j] : 0.0;
+    u16 h, l;
+    split_bf16((float)a, h, l);
+    M.s_hi[le] = h;
+    M.s_lo[le] = l;
+    if (with64) M.s64[le] = a;
+  }
+}
+
+// Gershgorin bound per matrix (one block per matrix)
+__global__ void b_gersh_kernel(const BMat* __restrict__ mats, const double* const* S, double* g) {
+  const int m = blockIdx.x;
+  const BMat& M = mats[m];
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < M.n; i += blockDim.x) {
+    const double* row = S[m] + (size_t)i * M.n;
+    double s = 0.0;
+    for (int j = 0; j < M.n; ++j) s += fabs(row[j]);
+    mx = fmax(mx, s);
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g[m] = red[0];
+}
+
+// Z0 (given, or I / sqrt(g)) into Z32, Zr and Zc of buffer 0
+__global__ void b_init_kernel(const BMat* __restrict__ mats, int count, const double* const* Z0,
+                              const double* __restrict__ g, const long long* __restrict__ off,
+                              long long total) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int m = find_matrix(off, count, e);
+    const BMat& M = mats[m];
+    const long long le = e - off[m];
+    const int i = (int)(le / M.np), j = (int)(le % M.np);
+    double v;
+    if (Z0[m]) v = (i < M.n && j < M.n) ? Z0[m][(size_t)i * M.n + j] : 0.0;
+    else v = (i == j && i < M.n) ? 1.0 / sqrt(g[m]) : 0.0;
+    const float f = (float)v;
+    u16 h, l;
+    split_bf16(f, h, l);
+    const size_t t = (size_t)j * M.np + i;
+    M.z32[0][le] = f;
+    M.zr_hi[0][le] = h;
+    M.zr_lo[0][le] = l;
+    M.zc_hi[0][t] = h;
+    M.zc_lo[0][t] = l;
+  }
+}
+
+// FP32 master -> FP64 row-major and transposed for matrices entering the FP64 phase
+__global__ void b_widen_kernel(const BMat* __restrict__ mats, int count,
+                               const long long* __restrict__ off, long long total) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int m = find_matrix(off, count, e);
+    const BMat& M = mats[m];
+    if (M.action != ACT_TRANSITION) continue;
+    const long long le = e - off[m];
+    const int i = (int)(le / M.np), j = (int)(le % M.np);
+    const double v = (double)M.z32[M.cur][le];
+    M.z64r[M.cur][le] = v;
+    M.z64c[M.cur][(size_t)j * M.np + i] = v;
+  }
+}
+
+// unpadded result: FP64 iterate if the FP64 phase ran, else the FP32 master
+__global__ void b_output_kernel(const BMat* __restrict__ mats, int count, double* const* Z,
+                                const long long* __restrict__ off, long long total, int from64) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int m = find_matrix(off, count, e);
+    const BMat& M = mats[m];
+    const long long le = e - off[m];
+    const int i = (int)(le / M.n), j = (int)(le % M.n);
+    const size_t src = (size_t)i * M.np + j;
+    Z[m][le] = from64 ? M.z64r[M.cur][src] : (double)M.z32[M.cur][src];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+// tile edge per order bucket: n <= g_tile_max[k] uses g_tile_edge[k]
+static int g_tile_nb = 4;
+static int g_tile_max[16] = {128, 256, 512, 1 << 30};
+static int g_tile_edge[16] = {64, 64, 128, 128};
+static bool g_use_graph = true;
+
+static int tile_for(int n) {
+  for (int k = 0; k < g_tile_nb; ++k)
+    if (n <= g_tile_max[k]) return g_tile_edge[k];
+  return 128;
+}
+
+static int rup(long long n, int g) { return (int)((n + g - 1) / g * g); }
+static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct BatchState {
+  int device = -1;
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  void* meta = nullptr;  // device: mats, tasks, offsets, pointer tables, partials, hist, scalars
+  size_t meta_bytes = 0;
+  int* pinned = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<char> key;  // layout the captured graph was built for
+};
+static BatchState g_b;
+
+static void batch_release() {
+  if (g_b.exec) (void)hipGraphExecDestroy(g_b.exec);
+  if (g_b.arena) (void)hipFree(g_b.arena);
+  if (g_b.meta) (void)hipFree(g_b.meta);
+  if (g_b.pinned) (void)hipHostFree(g_b.pinned);
+  if (g_b.cap) (void)hipStreamDestroy(g_b.cap);
+  g_b = BatchState();
+}
+
+static int grow(void** p, size_t* cap, size_t need) {
+  if (*cap >= need) return 0;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  const char* inject = getenv("ZF_FAULT_INJECT");
+  if (inject && strcmp(inject, "alloc") == 0)
+    return set_error(ZF_ERR_NOMEM, "allocation of %zu bytes refused (ZF_FAULT_INJECT=alloc)", need);
+  if (hipMalloc(p, need) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return set_error(ZF_ERR_NOMEM, "hipMalloc(%zu bytes) for the batch failed", need);
+  }
+  *cap = need;
+  return 0;
+}
+
+static int grid_for_total(long long total) {
+  long long g = (total + 255) / 256;
+  return (int)std::max(1LL, std::min(g, 65536LL));
+}
+
+struct Plan {
+  std::vector<BMat> mats;
+  std::vector<TileTask> full, sym;
+  std::vector<long long> off_pad, off_out;
+  long long total_pad = 0, total_out = 0, partials = 0;
+  size_t arena = 0;
+};
+
+// Buffer sizes for every matrix, task tables sorted by order (largest first).
+static void make_plan(int count, const int* n, bool with64, Plan& P) {
+  P.mats.resize(count);
+  size_t bytes = 0;
+  for (int m = 0; m < count; ++m) {
+    BMat& M = P.mats[m];
+    memset(&M, 0, sizeof M);
+    M.n = n[m];
+    M.tile = tile_for(n[m]);
+    M.np = rup(n[m], M.tile);
+    const int T = M.np / M.tile;
+    M.tiles_sym = T * (T + 1) / 2;
+    M.pbase = P.partials;
+    P.partials += M.tiles_sym;
+    P.off_pad.push_back(P.total_pad);
+    P.total_pad += (long long)M.np * M.np;
+    P.off_out.push_back(P.total_out);
+    P.total_out += (long long)M.n * M.n;
+    const size_t e = (size_t)M.np * M.np;
+    bytes += 16 * align256(e * 2) + 2 * align256(e * 4) + (with64 ? 7 * align256(e * 8) : 0);
+  }
+  P.arena = bytes;
+  std::vector<int> order(count);
+  for (int m = 0; m < count; ++m) order[m] = m;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return P.mats[a].np > P.mats[b].np; });
+  for (int m : order) {
+    const int T = P.mats[m].np / P.mats[m].tile;
+    for (int i = 0; i < T; ++i)
+      for (int j = 0; j < T; ++j) {
+        P.full.push_back(TileTask{m, (short)i, (short)j});
+        if (j >= i) P.sym.push_back(TileTask{m, (short)i, (short)j});
+      }
+  }
+}
+
+static void carve(Plan& P, char* base, bool with64) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base + o;
+    o += align256(bytes);
+    return p;
+  };
+  for (BMat& M : P.mats) {
+    const size_t e = (size_t)M.np * M.np;
+    M.s_hi = (u16*)take(e * 2);
+    M.s_lo = (u16*)take(e * 2);
+    for (int b = 0; b < 2; ++b) {
+      M.zr_hi[b] = (u16*)take(e * 2);
+      M.zr_lo[b] = (u16*)take(e * 2);
+      M.zc_hi[b] = (u16*)take(e * 2);
+      M.zc_lo[b] = (u16*)take(e * 2);
+    }
+    M.at_hi = (u16*)take(e * 2);
+    M.at_lo = (u16*)take(e * 2);
+    M.d_hi = (u16*)take(e * 2);
+    M.d_lo = (u16*)take(e * 2);
+    M.q_hi = (u16*)take(e * 2);
+    M.q_lo = (u16*)take(e * 2);
+    M.z32[0] = (float*)take(e * 4);
+    M.z32[1] = (float*)take(e * 4);
+    if (with64) {
+      M.s64 = (double*)take(e * 8);
+      M.z64r[0] = (double*)take(e * 8);
+      M.z64r[1] = (double*)take(e * 8);
+      M.z64c[0] = (double*)take(e * 8);
+      M.z64c[1] = (double*)take(e * 8);
+      M.a64t = (double*)take(e * 8);
+      M.d64 = (double*)take(e * 8);
+    }
+  }
+}
+
+struct Launch {
+  BMat* mats;
+  TileTask *full, *sym;
+  int nfull, nsym;
+  long long *off_pad;
+  long long total_pad;
+  double* partials;
+  int* remaining;
+  int count, grid, order, rule, max_l, max_h, refine_on, hist_cap;
+  double c1, c2;
+};
+
+// one macro-sweep on stream st (captured into the graph, or run eagerly)
+static hipError_t macro_sweep(const Launch& L, hipStream_t st) {
+  hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(L.grid, L.nfull)), dim3(256), 0, st, L.full,
+                     L.nfull, L.mats, (int)OP_L1, 0.0, 0.0, L.partials);
+  hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(L.grid, L.nsym)), dim3(256), 0, st, L.sym,
+                     L.nsym, L.mats, (int)OP_L2, 0.0, 0.0, L.partials);
+  if (L.refine_on) {
+    hipLaunchKernelGGL(grouped_f64_kernel, dim3(std::min(L.grid, L.nfull)), dim3(256), 0, st,
+                       L.full, L.nfull, L.mats, (int)OP_H1, L.partials);
+    hipLaunchKernelGGL(grouped_f64_kernel, dim3(std::min(L.grid, L.nsym)), dim3(256), 0, st, L.sym,
+                       L.nsym, L.mats, (int)OP_H2, L.partials);
+  }
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, st, L.mats, L.count, L.partials, L.order,
+                     L.rule, L.max_l, L.max_h, L.refine_on, L.hist_cap, L.remaining);
+  if (L.refine_on)
+    hipLaunchKernelGGL(b_widen_kernel, dim3(grid_for_total(L.total_pad)), dim3(256), 0, st, L.mats,
+                       L.count, L.off_pad, L.total_pad);
+  hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(L.grid, L.nsym)), dim3(256), 0, st, L.sym,
+                     L.nsym, L.mats, (int)OP_U3, L.c1, L.c2, L.partials);
+  hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(L.grid, L.nfull)), dim3(256), 0, st, L.full,
+                     L.nfull, L.mats, (int)OP_U4, 0.0, 0.0, L.partials);
+  return hipGetLastError();
+}
+
+static int batched_impl(int count, const double* const* S, const double* const* Z0, const int* n,
+                        const zf_opts& o, double* const* Z, zf_result* res, double* hist,
+                        int hist_cap, hipStream_t st) {
+  if (count <= 0 || !S || !Z || !n) return set_error(ZF_ERR_ARG, "bad batch arguments");
+  if (o.order != 2) return set_error(ZF_ERR_ARG, "the batched path supports order 2 (got %d)", o.order);
+  if (o.precision != ZF_BF16X3)
+    return set_error(ZF_ERR_ARG, "the batched path runs ZF_BF16X3 (got %d)", o.precision);
+  if (o.refine != ZF_REFINE_OFF && o.refine != ZF_REFINE_F64_DELTA)
+    return set_error(ZF_ERR_ARG, "the batched path supports refine off or F64_DELTA");
+  if (o.stop != ZF_STOP_RATIO && o.stop != ZF_STOP_MONOTONE)
+    return set_error(ZF_ERR_ARG, "unknown stop rule %d", o.stop);
+  if (hist_cap < 0 || (hist_cap > 0 && !hist)) return set_error(ZF_ERR_ARG, "bad hist buffer");
+  for (int m = 0; m < count; ++m) {
+    if (n[m] <= 0 || n[m] > 8192)
+      return set_error(ZF_ERR_ARG, "matrix %d: order %d outside 1..8192", m, n[m]);
+    if (!S[m] || !Z[m]) return set_error(ZF_ERR_ARG, "matrix %d: NULL S or Z", m);
+  }
+  const bool with64 = o.refine == ZF_REFINE_F64_DELTA;
+  const int max_l = o.max_sweeps > 0 ? o.max_sweeps : 100;
+  const int max_h = o.max_refine > 0 ? o.max_refine : 10;
+  const int hcap = std::max(hist_cap, 1);
+
+  int dev = 0;
+  BHIP_TRY(hipGetDevice(&dev));
+  if (g_b.device != dev) {
+    batch_release();
+    g_b.device = dev;
+  }
+  if (!g_b.cap) BHIP_TRY(hipStreamCreateWithFlags(&g_b.cap, hipStreamNonBlocking));
+  if (!g_b.pinned) BHIP_TRY(hipHostMalloc((void**)&g_b.pinned, 64, hipHostMallocDefault));
+
+  Plan P;
+  make_plan(count, n, with64, P);
+  int rc = grow(&g_b.arena, &g_b.arena_bytes, std::max<size_t>(P.arena, 256));
+  if (rc < 0) return rc;
+  carve(P, (char*)g_b.arena, with64);
+
+  // metadata block: mats | full tasks | sym tasks | off_pad | off_out | S, Z0, Z pointer
+  // tables | partials | hist | g | remaining
+  size_t o_mats = 0;
+  size_t o_full = align256(o_mats + sizeof(BMat) * count);
+  size_t o_sym = align256(o_full + sizeof(TileTask) * P.full.size());
+  size_t o_offp = align256(o_sym + sizeof(TileTask) * P.sym.size());
+  size_t o_offo = align256(o_offp + 8 * count);
+  size_t o_ps = align256(o_offo + 8 * count);
+  size_t o_pz0 = align256(o_ps + 8 * count);
+  size_t o_pz = align256(o_pz0 + 8 * count);
+  size_t o_part = align256(o_pz + 8 * count);
+  size_t o_hist = align256(o_part + 8 * P.partials);
+  size_t o_g = align256(o_hist + 8 * (size_t)count * hcap);
+  size_t o_rem = align256(o_g + 8 * count);
+  size_t total_meta = align256(o_rem + 64);
+  rc = grow(&g_b.meta, &g_b.meta_bytes, total_meta);
+  if (rc < 0) return rc;
+  char* mb = (char*)g_b.meta;
+  for (int m = 0; m < count; ++m) P.mats[m].hist = (double*)(mb + o_hist) + (size_t)m * hcap;
+
+  std::vector<const void*> ps(count), pz0(count), pz(count);
+  for (int m = 0; m < count; ++m) {
+    ps[m] = S[m];
+    pz0[m] = Z0 ? Z0[m] : nullptr;
+    pz[m] = Z[m];
+  }
+  // host -> device metadata (the host vectors outlive the synchronizing copies)
+  BHIP_TRY(hipMemcpyAsync(mb + o_mats, P.mats.data(), sizeof(BMat) * count, hipMemcpyHostToDevice, st));
+  BHIP_TRY(hipMemcpyAsync(mb + o_full, P.full.data(), sizeof(TileTask) * P.full.size(), hipMemcpyHostToDevice, st));
+  BHIP_TRY(hipMemcpyAsync(mb + o_sym, P.sym.data(), sizeof(TileTask) * P.sym.size(), hipMemcpyHostToDevice, st));
+  BHIP_TRY(hipMemcpyAsync(mb + o_offp, P.off_pad.data(), 8 * count, hipMemcpyHostToDevice, st));
+  BHIP_TRY(hipMemcpyAsync(mb + o_offo, P.off_out.data(), 8 * count, hipMemcpyHostToDevice, st));
+  BHIP_TRY(hipMemcpyAsync(mb + o_ps, ps.data(), 8 * count, hipMemcpyHostToDevice, st));
+  BHIP_TRY(hipMemcpyAsync(mb + o_pz0, pz0.data(), 8 * count, hipMemcpyHostToDevice, st));
+  BHIP_TRY(hipMemcpyAsync(mb + o_pz, pz.data(), 8 * count, hipMemcpyHostToDevice, st));
+
+  BMat* d_mats = (BMat*)(mb + o_mats);
+  const long long* d_offp = (const long long*)(mb + o_offp);
+  const long long* d_offo = (const long long*)(mb + o_offo);
+  const double* const* d_S = (const double* const*)(mb + o_ps);
+  const double* const* d_Z0 = (const double* const*)(mb + o_pz0);
+  double* const* d_Z = (double* const*)(mb + o_pz);
+  double* d_g = (double*)(mb + o_g);
+
+  // setup: operands of S and Z0
+  hipLaunchKernelGGL(b_split_kernel, dim3(grid_for_total(P.total_pad)), dim3(256), 0, st, d_mats,
+                     count, d_S, d_offp, P.total_pad, with64 ? 1 : 0);
+  hipLaunchKernelGGL(b_gersh_kernel, dim3(count), dim3(256), 0, st, d_mats, d_S, d_g);
+  hipLaunchKernelGGL(b_init_kernel, dim3(grid_for_total(P.total_pad)), dim3(256), 0, st, d_mats,
+                     count, d_Z0, d_g, d_offp, P.total_pad);
+  BHIP_TRY(hipGetLastError());
+
+  Launch L;
+  L.mats = d_mats;
+  L.full = (TileTask*)(mb + o_full);
+  L.sym = (TileTask*)(mb + o_sym);
+  L.nfull = (int)P.full.size();
+  L.nsym = (int)P.sym.size();
+  L.off_pad = (long long*)d_offp;
+  L.total_pad = P.total_pad;
+  L.partials = (double*)(mb + o_part);
+  L.remaining = (int*)(mb + o_rem);
+  L.count = count;
+  int cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+    cus = prop.multiProcessorCount;
+  L.grid = 2 * cus;
+  L.order = o.order;
+  L.rule = o.stop;
+  L.max_l = max_l;
+  L.max_h = max_h;
+  L.refine_on = with64 ? 1 : 0;
+  L.hist_cap = hcap;
+  L.c1 = 0.5;
+  L.c2 = 0.375;
+
+  // graph of one macro-sweep, rebuilt when the layout changes
+  std::vector<char> key(sizeof(Launch));
+  memcpy(key.data(), &L, sizeof(Launch));
+  if (g_use_graph && (g_b.key != key || !g_b.exec)) {
+    if (g_b.exec) {
+      (void)hipGraphExecDestroy(g_b.exec);
+      g_b.exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    BHIP_TRY(hipStreamBeginCapture(g_b.cap, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = macro_sweep(L, g_b.cap);
+    hipError_t ee = hipStreamEndCapture(g_b.cap, &graph);
+    if (ce != hipSuccess || ee != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return set_error(ZF_ERR_HIP, "graph capture failed: %s",
+                       hipGetErrorString(ce != hipSuccess ? ce : ee));
+    }
+    hipError_t ie = hipGraphInstantiate(&g_b.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      g_b.exec = nullptr;
+      return set_error(ZF_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    }
+    g_b.key = key;
+  }
+
+  const int max_macro = max_l + (with64 ? max_h + 1 : 0) + 2;
+  int sweeps = 0;
+  for (;;) {
+    if (g_use_graph) BHIP_TRY(hipGraphLaunch(g_b.exec, st));
+    else BHIP_TRY(macro_sweep(L, st));
+    BHIP_TRY(hipMemcpyAsync(g_b.pinned, L.remaining, sizeof(int), hipMemcpyDeviceToHost, st));
+    BHIP_TRY(hipStreamSynchronize(st));
+    ++sweeps;
+    if (g_b.pinned[0] == 0) break;
+    if (sweeps >= max_macro)
+      return set_error(ZF_ERR_HIP, "batched refinement did not finish in %d macro-sweeps", sweeps);
+  }
+  hipLaunchKernelGGL(b_output_kernel, dim3(grid_for_total(P.total_out)), dim3(256), 0, st, d_mats,
+                     count, d_Z, d_offo, P.total_out, with64 ? 1 : 0);
+  BHIP_TRY(hipGetLastError());
+  std::vector<BMat> out(count);
+  BHIP_TRY(hipMemcpyAsync(out.data(), d_mats, sizeof(BMat) * count, hipMemcpyDeviceToHost, st));
+  std::vector<double> h((size_t)count * hcap);
+  BHIP_TRY(hipMemcpyAsync(h.data(), mb + o_hist, 8 * h.size(), hipMemcpyDeviceToHost, st));
+  BHIP_TRY(hipStreamSynchronize(st));
+
+  int ret = 0, first_err = 0, first_m = -1;
+  for (int m = 0; m < count; ++m) {
+    const BMat& M = out[m];
+    const int len = std::min(M.hist_len, hist_cap);
+    for (int k = 0; k < len; ++k) hist[(size_t)m * hist_cap + k] = h[(size_t)m * hcap + k];
+    int flags = M.flags;
+    if (M.hist_len > hist_cap) flags |= ZF_WARN_HIST_TRUNC;
+    const double fe = with64 ? M.err_h : M.err_l;
+    int status = M.status;
+    if (status == 0 && !(fe < 1.0)) status = ZF_ERR_NOT_CONVERGED;
+    if (res) {
+      res[m].iters = M.upd_l + M.upd_h;
+      res[m].low_evals = M.evals_l;
+      res[m].high_evals = M.evals_h;
+      res[m].hist_len = len;
+      res[m].flags = flags;
+      res[m].final_err = fe;
+      res[m].final_rms = fe / sqrt((double)M.n);
+      res[m].status = status;
+    }
+    if (status < 0 && first_err == 0) {
+      first_err = status;
+      first_m = m;
+    }
+    ret |= flags;
+  }
+  if (first_err < 0)
+    return set_error(first_err, "matrix %d of the batch failed (status %d); see the results",
+                     first_m, first_err);
+  clear_error();
+  return ret;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: time the grouped BF16x3 GEMM (plain + symmetric) per order bucket
+// ---------------------------------------------------------------------------
+static int autotune_impl(const int* bucket_n, int nb, int batch, int reps, int* best,
+                         double* ms_out, hipStream_t st) {
+  if (nb <= 0 || nb > 16 || !bucket_n || batch <= 0 || reps <= 0)
+    return set_error(ZF_ERR_ARG, "bad autotune arguments");
+  const int cand[2] = {64, 128};
+  int dev = 0;
+  BHIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  BHIP_TRY(hipGetDeviceProperties(&prop, dev));
+  const int grid = 2 * prop.multiProcessorCount;
+  hipEvent_t e0, e1;
+  BHIP_TRY(hipEventCreate(&e0));
+  BHIP_TRY(hipEventCreate(&e1));
+  int rc = 0;
+  for (int b = 0; b < nb && rc == 0; ++b) {
+    double best_ms = 1e30;
+    best[b] = 128;
+    for (int c = 0; c < 2 && rc == 0; ++c) {
+      const int T = cand[c];
+      const int np = rup(bucket_n[b], T);
+      const int tiles = np / T;
+      std::vector<BMat> mats(batch);
+      std::vector<TileTask> full, sym;
+      const size_t e = (size_t)np * np;
+      void* buf = nullptr;
+      // per matrix: the operands of L1 / L2 only (zero data; timing does not depend on values)
+      const size_t per = 8 * align256(e * 2) + align256(8 * tiles * (tiles + 1) / 2);
+      if (hipMalloc(&buf, per * batch + 256) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = set_error(ZF_ERR_NOMEM, "autotune allocation failed");
+        break;
+      }
+      (void)hipMemsetAsync(buf, 0, per * batch + 256, st);
+      char* p = (char*)buf;
+      for (int m = 0; m < batch; ++m) {
+        BMat& M = mats[m];
+        memset(&M, 0, sizeof M);
+        M.n = bucket_n[b];
+        M.np = np;
+        M.tile = T;
+        M.tiles_sym = tiles * (tiles + 1) / 2;
+        u16* q[8];
+        for (int k = 0; k < 8; ++k) {
+          q[k] = (u16*)p;
+          p += align256(e * 2);
+        }
+        M.zc_hi[0] = q[0];
+        M.zc_lo[0] = q[1];
+        M.s_hi = q[2];
+        M.s_lo = q[3];
+        M.at_hi = q[4];
+        M.at_lo = q[5];
+        M.d_hi = q[6];
+        M.d_lo = q[7];
+        M.pbase = 0;
+        M.phase = PH_LOW;
+        M.action = ACT_EVAL;
+        for (int i = 0; i < tiles; ++i)
+          for (int j = 0; j < tiles; ++j) {
+            full.push_back(TileTask{m, (short)i, (short)j});
+            if (j >= i) sym.push_back(TileTask{m, (short)i, (short)j});
+          }
+        p += align256(8 * tiles * (tiles + 1) / 2);
+      }
+      void* meta = nullptr;
+      const size_t mbytes = align256(sizeof(BMat) * batch) + align256(sizeof(TileTask) * full.size()) +
+                            align256(sizeof(TileTask) * sym.size()) + align256(8 * (size_t)tiles * tiles);
+      if (hipMalloc(&meta, mbytes) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(buf);
+        rc = set_error(ZF_ERR_NOMEM, "autotune allocation failed");
+        break;
+      }
+      char* mp = (char*)meta;
+      BMat* dm = (BMat*)mp;
+      TileTask* df = (TileTask*)(mp + align256(sizeof(BMat) * batch));
+      TileTask* ds = (TileTask*)((char*)df + align256(sizeof(TileTask) * full.size()));
+      double* dpart = (double*)((char*)ds + align256(sizeof(TileTask) * sym.size()));
+      (void)hipMemcpyAsync(dm, mats.data(), sizeof(BMat) * batch, hipMemcpyHostToDevice, st);
+      (void)hipMemcpyAsync(df, full.data(), sizeof(TileTask) * full.size(), hipMemcpyHostToDevice, st);
+      (void)hipMemcpyAsync(ds, sym.data(), sizeof(TileTask) * sym.size(), hipMemcpyHostToDevice, st);
+      // every matrix uses partial base 0: timing only, the sums are discarded
+      for (int r = 0; r <= reps; ++r) {
+        if (r == 1) (void)hipEventRecord(e0, st);
+        hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(grid, (int)full.size())), dim3(256), 0,
+                           st, df, (int)full.size(), dm, (int)OP_L1, 0.0, 0.0, dpart);
+        hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(grid, (int)sym.size())), dim3(256), 0,
+                           st, ds, (int)sym.size(), dm, (int)OP_L2, 0.0, 0.0, dpart);
+      }
+      (void)hipEventRecord(e1, st);
+      hipError_t he = hipEventSynchronize(e1);
+      float t = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+      (void)hipFree(meta);
+      (void)hipFree(buf);
+      if (he != hipSuccess) {
+        rc = set_error(ZF_ERR_HIP, "autotune timing: %s", hipGetErrorString(he));
+        break;
+      }
+      const double ms = t / reps;
+      if (ms_out) ms_out[2 * b + c] = ms;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best[b] = T;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc < 0) return rc;
+  g_tile_nb = nb;
+  for (int b = 0; b < nb; ++b) {
+    g_tile_max[b] = (b == nb - 1) ? (1 << 30) : bucket_n[b];
+    g_tile_edge[b] = best[b];
+  }
+  g_b.key.clear();  // layouts change with the table
+  clear_error();
+  return 0;
+}
+
+void batch_release_all() { batch_release(); }
+
+}  // namespace zf
+
+using namespace zf;
+
+extern "C" {
+
+int zf_refine_batched(int count, const double* const* S, const double* const* Z0, const int* n,
+                      const zf_opts* opts, double* const* Z, zf_result* res, double* hist,
+                      int hist_cap, void* stream) {
+  zf_opts o;
+  zf_default_opts(&o);
+  if (opts) o = *opts;
+  return batched_impl(count, S, Z0, n, o, Z, res, hist, hist_cap, (hipStream_t)stream);
+}
+
+int zf_batched_set_tiles(const int* max_n, const int* tile, int count) {
+  if (count <= 0 || count > 16 || !max_n || !tile)
+    return set_error(ZF_ERR_ARG, "tile table needs 1..16 entries");
+  for (int k = 0; k < count; ++k)
+    if (tile[k] != 64 && tile[k] != 128) return set_error(ZF_ERR_ARG, "tile edges are 64 or 128");
+  g_tile_nb = count;
+  for (int k = 0; k < count; ++k) {
+    g_tile_max[k] = (k == count - 1) ? (1 << 30) : max_n[k];
+    g_tile_edge[k] = tile[k];
+  }
+  g_b.key.clear();
+  return 0;
+}
+
+int zf_batched_get_tiles(int* max_n, int* tile, int cap) {
+  if (!max_n || !tile || cap < g_tile_nb) return set_error(ZF_ERR_ARG, "table needs %d entries", g_tile_nb);
+  for (int k = 0; k < g_tile_nb; ++k) {
+    max_n[k] = g_tile_max[k];
+    tile[k] = g_tile_edge[k];
+  }
+  return g_tile_nb;
+}
+
+int zf_batched_autotune(const int* bucket_n, int nbuckets, int batch, int reps, int* best_tile,
+                        double* ms, void* stream) {
+  return autotune_impl(bucket_n, nbuckets, batch, reps, best_tile, ms, (hipStream_t)stream);
+}
+
+void zf_batched_use_graph(int on) { g_use_graph = on != 0; }
+
+void zf_batched_release(void) { batch_release(); }
+
+}  // extern "C"

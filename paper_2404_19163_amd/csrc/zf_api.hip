@@ -20,6 +20,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -30,7 +31,7 @@ namespace zf {
 
 static thread_local std::string g_err;
 
-static int fail(int code, const char* fmt, ...) {
+int set_error(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -39,6 +40,10 @@ static int fail(int code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
+
+void clear_error() { g_err.clear(); }
+
+#define fail set_error
 
 #define HIP_TRY(expr)                                                                       \
   do {                                                                                      \
@@ -127,6 +132,8 @@ struct Workspace {
   double *q64 = nullptr, *u64 = nullptr;
   // scalars
   double *partials = nullptr, *err_dev = nullptr, *rowsum = nullptr, *g_dev = nullptr;
+  double *gscr = nullptr, *cg = nullptr;  // learned-guess scratch (8192) and coefficients (8)
+  float* feats = nullptr;
   double* host_err = nullptr;  // pinned
 };
 
@@ -177,6 +184,9 @@ static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out) {
     ZF_TRY(ws_alloc(w, &w.err_dev, 8));
     ZF_TRY(ws_alloc(w, &w.rowsum, np_new));
     ZF_TRY(ws_alloc(w, &w.g_dev, 8));
+    ZF_TRY(ws_alloc(w, &w.gscr, 8192));
+    ZF_TRY(ws_alloc(w, &w.cg, 8));
+    ZF_TRY(ws_alloc(w, &w.feats, 64));
     HIP_TRY(hipHostMalloc((void**)&w.host_err, 8 * sizeof(double), hipHostMallocDefault));
     // the BF16 pairs of delta and Q and the row-major Z pair serve both phases
     ZF_TRY(ws_alloc(w, &w.d_hi, m));
@@ -239,7 +249,7 @@ static int gemm_x3(const u16* Ah, const u16* Al, const u16* Bh, const u16* Bl, i
     pe.b = take_event();
     pe.cls = sym ? K_X3_SYM : K_X3;
     // executed MFMA flops: 3 products of 2 * tile^2 * K per launched tile
-    const double t = (double)x3_tile(np, np, sym);
+    const double t = (double)x3_tile_edge(np, np, sym);
     pe.flops = 3.0 * 2.0 * (double)x3_blocks(np, np, sym) * t * t * (double)np;
     HIP_TRY(hipEventRecord(pe.a, st));
   }
@@ -443,6 +453,47 @@ static int run_phase(Ctx& c, bool high, bool x3corr, int stop_rule, int max_upda
   }
 }
 
+// Learned guess into buffer 0 (every layout the first phase reads): S^2 by the
+// symmetric matrix-core GEMM, features, network, acceptance on the host.  Returns 1
+// when the guess was written, 0 to fall back to the scaled identity.
+static int learned_guess(Ctx& c, const double* S, bool mixed, bool use_h, hipStream_t st) {
+  Workspace& w = *c.w;
+  const int n = c.n, np = c.np;
+  if (!net_ready()) return 0;
+  const double* S2d = nullptr;
+  const float* S2f = nullptr;
+  if (mixed) {  // BF16x3 S^2 into the second FP32 master (free until the first update)
+    EpiParams e = epi0(np, n);
+    e.o32 = e.ot32 = w.z32[1];
+    ZF_TRY(gemm_x3(w.s_hi, w.s_lo, w.s_hi, w.s_lo, np, true, e, st));
+    S2f = w.z32[1];
+  } else {  // FP64 S^2 into A^T's buffer (free until the first residual)
+    EpiParams e = epi0(np, n);
+    e.o64 = e.ot64 = w.a64t;
+    ZF_TRY(gemm_f64(w.s64, w.s64, np, true, e, st));
+    S2d = w.a64t;
+  }
+  ZF_TRY(guess_features(S, n, S2d, S2f, np, w.s64, w.feats, w.gscr, st));
+  ZF_TRY(guess_infer(w.feats, w.cg, st));
+  double hv[8];
+  HIP_TRY(hipMemcpyAsync(hv, w.cg, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hv + 3, w.gscr, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double cf[3] = {hv[0], hv[1], hv[2]};
+  const double g = hv[3], glo = hv[4];
+  if (!(g > 0.0) || !isfinite(cf[0]) || !isfinite(cf[1]) || !isfinite(cf[2])) return 0;
+  if (!guess_accept(cf, glo > 0.0 ? glo / g : 0.0)) return 0;
+  double cgh[4] = {cf[0], cf[1], cf[2], g};
+  HIP_TRY(hipMemcpyAsync(w.cg + 4, cgh, sizeof cgh, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_guess_write(S, n, S2d, S2f, np, w.cg + 4, mixed ? w.z32[0] : nullptr,
+                             use_h ? w.z64r[0] : nullptr, use_h ? w.z64c[0] : nullptr, w.zr_hi[0],
+                             w.zr_lo[0], mixed ? w.zc_hi[0] : nullptr, mixed ? w.zc_lo[0] : nullptr,
+                             st));
+  // the host copy cgh must outlive the asynchronous copy
+  HIP_TRY(hipStreamSynchronize(st));
+  return 1;
+}
+
 static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& o, double* Z,
                        zf_result* res, double* hist, int hist_cap, hipStream_t st) {
   if (!S || !Z) return fail(ZF_ERR_ARG, "S and Z must be non-NULL device pointers");
@@ -457,12 +508,14 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(ZF_ERR_ARG, "bad hist buffer");
   if (n > 46000) return fail(ZF_ERR_ARG, "n = %d exceeds the supported maximum 46000", n);
 
+  if (o.z0 != 0 && o.z0 != 1) return fail(ZF_ERR_ARG, "unknown guess kind %d", o.z0);
   const bool mixed = o.precision != ZF_FP64;
   const bool use_h = !mixed || o.refine != ZF_REFINE_OFF;
   const bool x3corr = mixed && o.refine == ZF_REFINE_F64_DELTA;
+  const bool learned = !Z0 && o.z0 == 1;
   const int np = pad_order(n);
   Workspace* w = nullptr;
-  ZF_TRY(ws_get(np, mixed, use_h, &w));
+  ZF_TRY(ws_get(np, mixed, use_h || learned, &w));
 
   Ctx c;
   c.w = w;
@@ -476,11 +529,21 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
 
   // setup: operands of S, then Z0
   HIP_TRY(launch_split_pad(S, n, n, np, mixed ? w->s_hi : nullptr, mixed ? w->s_lo : nullptr,
-                           use_h ? w->s64 : nullptr, nullptr, false, 1, st));
+                           (use_h || learned) ? w->s64 : nullptr, nullptr, false, 1, st));
+  int z0_used = Z0 ? 0 : 1;
+  int guess_flags = 0;
+  if (learned) {
+    int lr = learned_guess(c, S, mixed, use_h, st);
+    if (lr < 0) return lr;
+    if (lr == 1) z0_used = 2;
+    else guess_flags |= ZF_WARN_Z0_FALLBACK;
+  }
   if (Z0) {
     HIP_TRY(launch_init_given(Z0, n, np, mixed ? w->z32[0] : nullptr, use_h ? w->z64r[0] : nullptr,
                               use_h ? w->z64c[0] : nullptr, w->zr_hi[0], w->zr_lo[0],
                               mixed ? w->zc_hi[0] : nullptr, mixed ? w->zc_lo[0] : nullptr, st));
+  } else if (z0_used == 2) {
+    // written by learned_guess
   } else {
     HIP_TRY(launch_row_abs_max(S, n, n, w->rowsum, w->g_dev, st));
     HIP_TRY(launch_init_identity(w->g_dev, n, np, mixed ? w->z32[0] : nullptr,
@@ -492,7 +555,7 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   std::vector<double> h;
   int cur = 0;
   PhaseOut pl, ph;
-  int flags = 0;
+  int flags = guess_flags;
   int rc = 0;
   if (mixed) {
     rc = run_phase(c, false, false, o.stop, max_l, cur, h, pl);
@@ -528,14 +591,18 @@ done:
       res->flags = flags;
       res->final_err = use_h ? ph.err : pl.err;
       res->final_rms = res->final_err / sqrt((double)n);
+      res->status = rc < 0 ? rc : 0;
+      res->z0_used = z0_used;
     }
   }
   if (rc < 0) return rc;
   const double fe = use_h ? ph.err : pl.err;
-  if (!(fe < 1.0))
+  if (!(fe < 1.0)) {
+    if (res) res->status = ZF_ERR_NOT_CONVERGED;
     return fail(ZF_ERR_NOT_CONVERGED,
                 "||Z^T S Z - I||_F = %g >= 1: the guess violates ||X0 - I||_2 < 1 or S is not SPD",
                 fe);
+  }
   g_err.clear();
   return flags;
 }
@@ -554,6 +621,7 @@ void zf_default_opts(zf_opts* o) {
   o->max_sweeps = 100;
   o->refine = ZF_REFINE_F64_DELTA;
   o->max_refine = 10;
+  o->z0 = 0;
 }
 
 int zf_refine_ex(const double* S, const double* Z0, int n, const zf_opts* opts, double* Z,
@@ -604,6 +672,7 @@ int zf_residual(const double* S, const double* Z, int n, double* err_f, void* st
 }
 
 void zf_release(void) {
+  batch_release_all();
   if (g_ws.device >= 0) ws_free(g_ws);
   g_ws.device = -1;
   for (auto& p : g_prof.pending) {
@@ -617,7 +686,7 @@ void zf_release(void) {
 
 const char* zf_last_error(void) { return g_err.c_str(); }
 
-int zf_version(void) { return 1; }
+int zf_version(void) { return 2; }
 
 // ---- per-kernel timing ------------------------------------------------------
 void zf_profile_enable(int on) { g_prof.on = on != 0; }
@@ -637,6 +706,84 @@ int zf_profile_read(int cls, const char** name, long long* launches, double* tot
   if (launches) *launches = g_prof.launches[cls];
   if (total_ms) *total_ms = g_prof.ms[cls];
   if (flops) *flops = g_prof.flops[cls];
+  return 0;
+}
+
+// ---- learned-guess helpers -----------------------------------------------------
+int zf_features(const double* S, int n, float* feats, void* stream) {
+  if (!S || !feats || n <= 0) return fail(ZF_ERR_ARG, "bad feature arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const int np = pad_order(n);
+  Workspace* w = nullptr;
+  ZF_TRY(ws_get(np, false, true, &w));
+  HIP_TRY(launch_split_pad(S, n, n, np, nullptr, nullptr, w->s64, nullptr, false, 1, st));
+  EpiParams e = epi0(np, n);
+  e.o64 = e.ot64 = w->a64t;
+  ZF_TRY(gemm_f64(w->s64, w->s64, np, true, e, st));
+  ZF_TRY(guess_features(S, n, w->a64t, nullptr, np, w->s64, feats, w->gscr, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  g_err.clear();
+  return 0;
+}
+
+// 3x3 solve by Gaussian elimination with partial pivoting
+static bool solve3(double A[3][3], double b[3], double x[3]) {
+  int p[3] = {0, 1, 2};
+  for (int k = 0; k < 3; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < 3; ++i)
+      if (fabs(A[p[i]][k]) > fabs(A[p[piv]][k])) piv = i;
+    std::swap(p[k], p[piv]);
+    if (A[p[k]][k] == 0.0) return false;
+    for (int i = k + 1; i < 3; ++i) {
+      const double f = A[p[i]][k] / A[p[k]][k];
+      for (int j = k; j < 3; ++j) A[p[i]][j] -= f * A[p[k]][j];
+      b[p[i]] -= f * b[p[k]];
+    }
+  }
+  for (int k = 2; k >= 0; --k) {
+    double s = b[p[k]];
+    for (int j = k + 1; j < 3; ++j) s -= A[p[k]][j] * x[j];
+    x[k] = s / A[p[k]][k];
+  }
+  return true;
+}
+
+int zf_guess_label(const double* S, const double* Z, int n, double* c, void* stream) {
+  if (!S || !Z || !c || n <= 0) return fail(ZF_ERR_ARG, "bad label arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const int np = pad_order(n);
+  Workspace* w = nullptr;
+  ZF_TRY(ws_get(np, false, true, &w));
+  // S, Z padded; S^2 in a64t, S^3 in d64 (both symmetric)
+  HIP_TRY(launch_split_pad(S, n, n, np, nullptr, nullptr, w->s64, nullptr, false, 1, st));
+  HIP_TRY(launch_init_given(Z, n, np, nullptr, w->z64r[0], w->z64c[0], w->zr_hi[0], w->zr_lo[0],
+                            nullptr, nullptr, st));
+  EpiParams e = epi0(np, n);
+  e.o64 = e.ot64 = w->a64t;
+  ZF_TRY(gemm_f64(w->s64, w->s64, np, true, e, st));
+  EpiParams e3 = epi0(np, n);
+  e3.o64 = e3.ot64 = w->d64;
+  ZF_TRY(gemm_f64(w->a64t, w->s64, np, true, e3, st));
+  const double* a[7] = {w->s64, w->s64, w->a64t, w->a64t, w->s64, w->a64t, w->d64};
+  const double* b[7] = {w->s64, w->a64t, w->a64t, w->d64, w->z64r[0], w->z64r[0], w->z64r[0]};
+  ZF_TRY(gersh_stats(S, n, w->gscr, st));
+  ZF_TRY(dots8(a, b, 7, n, np, w->gscr + 8, w->gscr + 16, st));
+  double hv[16];
+  HIP_TRY(hipMemcpyAsync(hv, w->gscr, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double g = hv[0];
+  // t[k] = tr(S^k) for k = 1..5; u[j] = <S^j, Z> = tr(S^j Z) for j = 1..3
+  const double t[6] = {0.0, hv[3], hv[8], hv[9], hv[10], hv[11]};
+  const double u[4] = {0.0, hv[12], hv[13], hv[14]};
+  double A[3][3], r[3], x[3];
+  for (int j = 0; j < 3; ++j) {
+    for (int k = 0; k < 3; ++k) A[j][k] = t[j + k + 1] / pow(g, j + k + 1);
+    r[j] = sqrt(g) * u[j + 1] / pow(g, j + 1);
+  }
+  if (!solve3(A, r, x)) return fail(ZF_ERR_NONFINITE, "singular label system");
+  for (int k = 0; k < 3; ++k) c[k] = x[k];
+  g_err.clear();
   return 0;
 }
 

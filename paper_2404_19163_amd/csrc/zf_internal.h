@@ -74,7 +74,7 @@ struct EpiParams {
 // multiples of kTile; the caller pads.  Symmetric mode requires M == N.
 constexpr int kTile = 128;
 int num_tiles(int M, int N, bool sym);   // blocks of the FP64 kernel (kTile tiles)
-int x3_tile(int M, int N, bool sym);     // tile edge the BF16x3 launch will use
+int x3_tile_edge(int M, int N, bool sym);  // tile edge the BF16x3 launch will use
 int x3_blocks(int M, int N, bool sym);   // blocks (= norm partials) of that launch
 
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
@@ -102,5 +102,24 @@ hipError_t launch_unpad_f64(const double* src, int np, int n, double* dst, hipSt
 hipError_t launch_unpad_f32(const float* src, int np, int n, double* dst, hipStream_t st);
 hipError_t launch_norm_finalize(const double* partials, int count, double* out, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+// Error reporting shared by the translation units (zf_api.hip): set the thread's
+// message and return code; clear_error() empties it.
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+void batch_release_all();  // frees the batched path's cached state (batched.hip)
+
+// learned guess (guess.hip)
+int guess_features(const double* S, int n, const double* S2, const float* S2f, int np,
+                   const double* S64pad, float* feats, double* scratch, hipStream_t st);
+int guess_infer(const float* feats, double* coef, hipStream_t st);
+bool net_ready();
+bool guess_accept(double c[3], double x_lo);
+hipError_t launch_guess_write(const double* S, int n, const double* S2, const float* S2f, int np,
+                              const double* cg, float* z32, double* z64r, double* z64c, u16* zr_hi,
+                              u16* zr_lo, u16* zc_hi, u16* zc_lo, hipStream_t st);
+int dots8(const double* const* a, const double* const* b, int count, int n, int np, double* out_dev,
+          double* partial, hipStream_t st);
+int gersh_stats(const double* S, int n, double* out_dev, hipStream_t st);
 
 }  // namespace zf

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libzf.so")
 FP64, BF16X3, FP16X3 = 0, 1, 2
 STOP_RATIO, STOP_MONOTONE = 0, 1
 REFINE_OFF, REFINE_F64_DELTA, REFINE_F64_FULL = 0, 1, 2
-WARN_MAXSWEEPS, WARN_HIST_TRUNC = 1, 4
+WARN_MAXSWEEPS, WARN_Z0_FALLBACK, WARN_HIST_TRUNC = 1, 2, 4
+Z0_GIVEN, Z0_SCALED_IDENTITY, Z0_LEARNED = 0, 1, 2
 ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NONFINITE, ERR_NOT_CONVERGED = -1, -2, -3, -4, -5
 
 _PREC = {"fp64": FP64, "bf16x3": BF16X3, "fp16x3": FP16X3}
@@ -39,19 +40,25 @@ class ZFError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("precision", ctypes.c_int), ("stop", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("refine", ctypes.c_int),
-                ("max_refine", ctypes.c_int)]
+                ("max_refine", ctypes.c_int), ("z0", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("low_evals", ctypes.c_int),
                 ("high_evals", ctypes.c_int), ("hist_len", ctypes.c_int),
                 ("flags", ctypes.c_int), ("final_err", ctypes.c_double),
-                ("final_rms", ctypes.c_double)]
+                ("final_rms", ctypes.c_double), ("status", ctypes.c_int),
+                ("z0_used", ctypes.c_int)]
 
 
 EXPORTS = ("zf_default_opts", "zf_refine", "zf_refine_ex", "zf_residual", "zf_release",
            "zf_last_error", "zf_version", "zf_t_split", "zf_t_gemm", "zf_t_gershgorin",
-           "zf_profile_enable", "zf_profile_reset", "zf_profile_read")
+           "zf_profile_enable", "zf_profile_reset", "zf_profile_read", "zf_refine_batched",
+           "zf_batched_set_tiles", "zf_batched_get_tiles", "zf_batched_autotune",
+           "zf_batched_use_graph", "zf_batched_release", "zf_features", "zf_guess_label",
+           "zf_mlp_set_params", "zf_mlp_get_params", "zf_mlp_set_norm", "zf_mlp_train_step",
+           "zf_mlp_grad", "zf_mlp_predict")
+N_PARAMS = 4931
 
 _lib = None
 
@@ -92,6 +99,35 @@ def lib() -> ctypes.CDLL:
     L.zf_profile_reset.restype = None
     L.zf_profile_read.argtypes = [i, P(ctypes.c_char_p), P(ctypes.c_longlong), P(d), P(d)]
     L.zf_profile_read.restype = i
+    L.zf_refine_batched.argtypes = [i, P(vp), P(vp), P(i), P(Opts), P(vp), P(Result), P(d), i, vp]
+    L.zf_refine_batched.restype = i
+    L.zf_batched_set_tiles.argtypes = [P(i), P(i), i]
+    L.zf_batched_set_tiles.restype = i
+    L.zf_batched_get_tiles.argtypes = [P(i), P(i), i]
+    L.zf_batched_get_tiles.restype = i
+    L.zf_batched_autotune.argtypes = [P(i), i, i, i, P(i), P(d), vp]
+    L.zf_batched_autotune.restype = i
+    L.zf_batched_use_graph.argtypes = [i]
+    L.zf_batched_use_graph.restype = None
+    L.zf_batched_release.argtypes = []
+    L.zf_batched_release.restype = None
+    F = P(ctypes.c_float)
+    L.zf_features.argtypes = [vp, i, vp, vp]
+    L.zf_features.restype = i
+    L.zf_guess_label.argtypes = [vp, vp, i, P(d), vp]
+    L.zf_guess_label.restype = i
+    L.zf_mlp_set_params.argtypes = [F, i]
+    L.zf_mlp_set_params.restype = i
+    L.zf_mlp_get_params.argtypes = [F, i]
+    L.zf_mlp_get_params.restype = i
+    L.zf_mlp_set_norm.argtypes = [F, F, F, F]
+    L.zf_mlp_set_norm.restype = i
+    L.zf_mlp_train_step.argtypes = [vp, vp, i, ctypes.c_float, F, vp]
+    L.zf_mlp_train_step.restype = i
+    L.zf_mlp_grad.argtypes = [vp, vp, i, F, F, vp]
+    L.zf_mlp_grad.restype = i
+    L.zf_mlp_predict.argtypes = [vp, P(d), vp]
+    L.zf_mlp_predict.restype = i
     _lib = L
     return L
 
@@ -130,27 +166,101 @@ class Refined:
     flags: int = 0
     final_err: float = math.nan
     final_rms: float = math.nan
+    status: int = 0
+    z0_used: int = -1
 
 
 def refine(S: torch.Tensor, Z0: torch.Tensor | None = None, *, order: int = 2,
            precision: str = "bf16x3", stop: str = "ratio", max_sweeps: int = 100,
            refine: str = "f64_delta", max_refine: int = 10, out: torch.Tensor | None = None,
-           hist_cap: int = 256, stream=None) -> Refined:
-    """Refine Z0 (None: scaled identity) to Z with Z^T S Z = I (zf_refine_ex)."""
+           hist_cap: int = 256, stream=None, guess: str = "identity") -> Refined:
+    """Refine Z0 to Z with Z^T S Z = I (zf_refine_ex).  With Z0 None the guess is the
+    scaled identity, or the learned polynomial (guess="learned", needs a loaded net)."""
     n = S.shape[0]
     s_ptr = _dev(S, "S", n)
     z0_ptr = _dev(Z0, "Z0", n) if Z0 is not None else None
     if out is None:
         out = torch.empty_like(S)
     z_ptr = _dev(out, "out", n)
-    o = Opts(order, _PREC[precision], _STOP[stop], max_sweeps, _REFINE[refine], max_refine)
+    o = Opts(order, _PREC[precision], _STOP[stop], max_sweeps, _REFINE[refine], max_refine,
+             1 if guess == "learned" else 0)
     r = Result()
     hist = (ctypes.c_double * max(hist_cap, 1))()
     rc = lib().zf_refine_ex(s_ptr, z0_ptr, n, ctypes.byref(o), z_ptr, ctypes.byref(r), hist,
                             hist_cap, _stream(stream))
     _check(rc)
-    return Refined(out, r.iters, list(hist[: r.hist_len]), r.low_evals, r.high_evals, r.flags,
-                   r.final_err, r.final_rms)
+    res = Refined(out, r.iters, list(hist[: r.hist_len]), r.low_evals, r.high_evals, r.flags,
+                  r.final_err, r.final_rms)
+    res.z0_used = r.z0_used
+    return res
+
+
+@dataclass
+class BatchResult:
+    results: list
+    rc: int
+
+
+def refine_batched(S_list, Z0_list=None, *, order: int = 2, precision: str = "bf16x3",
+                   stop: str = "ratio", max_sweeps: int = 100, refine: str = "f64_delta",
+                   max_refine: int = 10, out=None, hist_cap: int = 64, stream=None,
+                   raise_on_error: bool = True) -> BatchResult:
+    """Refine many matrices together (zf_refine_batched).  Returns one Refined per
+    matrix (with .status) and the call's return code."""
+    count = len(S_list)
+    ns = [int(S.shape[0]) for S in S_list]
+    sp = (ctypes.c_void_p * count)(*[_dev(S, "S", n) for S, n in zip(S_list, ns)])
+    if Z0_list is None:
+        z0p = None
+    else:
+        z0p = (ctypes.c_void_p * count)(*[(_dev(Z, "Z0", n) if Z is not None else None)
+                                          for Z, n in zip(Z0_list, ns)])
+    if out is None:
+        out = [torch.empty_like(S) for S in S_list]
+    zp = (ctypes.c_void_p * count)(*[_dev(Z, "out", n) for Z, n in zip(out, ns)])
+    narr = (ctypes.c_int * count)(*ns)
+    o = Opts(order, _PREC[precision], _STOP[stop], max_sweeps, _REFINE[refine], max_refine, 0)
+    res = (Result * count)()
+    hist = (ctypes.c_double * max(count * hist_cap, 1))()
+    rc = lib().zf_refine_batched(count, sp, z0p, narr, ctypes.byref(o), zp, res, hist, hist_cap,
+                                 _stream(stream))
+    if rc < 0 and raise_on_error:
+        raise ZFError(rc, lib().zf_last_error().decode())
+    outl = []
+    for m in range(count):
+        r = res[m]
+        h = list(hist[m * hist_cap: m * hist_cap + r.hist_len])
+        outl.append(Refined(out[m], r.iters, h, r.low_evals, r.high_evals, r.flags, r.final_err,
+                            r.final_rms))
+        outl[-1].status = r.status
+    return BatchResult(outl, rc)
+
+
+def batched_set_tiles(max_n, tiles) -> None:
+    k = len(max_n)
+    _check(lib().zf_batched_set_tiles((ctypes.c_int * k)(*max_n), (ctypes.c_int * k)(*tiles), k))
+
+
+def batched_get_tiles():
+    mx = (ctypes.c_int * 16)()
+    tl = (ctypes.c_int * 16)()
+    k = _check(lib().zf_batched_get_tiles(mx, tl, 16))
+    return list(mx[:k]), list(tl[:k])
+
+
+def batched_autotune(bucket_n, batch: int = 32, reps: int = 5, stream=None):
+    """Time 64- and 128-wide tiles per order bucket, install the faster; returns
+    (tiles, [(ms64, ms128), ...])."""
+    k = len(bucket_n)
+    best = (ctypes.c_int * k)()
+    ms = (ctypes.c_double * (2 * k))()
+    _check(lib().zf_batched_autotune((ctypes.c_int * k)(*bucket_n), k, batch, reps, best, ms,
+                                     _stream(stream)))
+    return list(best), [(ms[2 * b], ms[2 * b + 1]) for b in range(k)]
+
+
+def batched_use_graph(on: bool = True) -> None:
+    lib().zf_batched_use_graph(1 if on else 0)
 
 
 def refine_basic(S, Z0, order, precision, out, hist_cap=256, stream=None):
@@ -245,3 +355,77 @@ def profile_read() -> dict:
                                      ctypes.byref(fl)))
         out[name.value.decode()] = (n.value, ms.value, fl.value)
     return out
+
+
+# ---- learned guess -----------------------------------------------------------
+def _f32p(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def features(S: torch.Tensor, stream=None) -> torch.Tensor:
+    """The 8 spectral features of S (device FP32 tensor)."""
+    n = S.shape[0]
+    f = torch.empty(8, dtype=torch.float32, device=S.device)
+    _check(lib().zf_features(_dev(S, "S", n), n, f.data_ptr(), _stream(stream)))
+    return f
+
+
+def guess_label(S: torch.Tensor, Z: torch.Tensor, stream=None):
+    """Least-squares coefficients of p in the S^(1/2)-weighted norm (3 floats)."""
+    n = S.shape[0]
+    c = (ctypes.c_double * 3)()
+    _check(lib().zf_guess_label(_dev(S, "S", n), _dev(Z, "Z", n), n, c, _stream(stream)))
+    return [c[0], c[1], c[2]]
+
+
+def mlp_set_params(theta) -> None:
+    a, p = _f32p(theta)
+    if a.size != N_PARAMS:
+        raise ValueError(f"expected {N_PARAMS} parameters")
+    _check(lib().zf_mlp_set_params(p, N_PARAMS))
+
+
+def mlp_get_params():
+    import numpy as np
+    a = np.empty(N_PARAMS, dtype=np.float32)
+    _check(lib().zf_mlp_get_params(a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), N_PARAMS))
+    return a
+
+
+def mlp_set_norm(mu_x, sd_x, mu_y, sd_y) -> None:
+    arrs = [_f32p(x) for x in (mu_x, sd_x, mu_y, sd_y)]
+    _check(lib().zf_mlp_set_norm(*[p for _, p in arrs]))
+
+
+def _f32dev(t: torch.Tensor, cols: int, name: str) -> int:
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2 \
+            or t.shape[1] != cols:
+        raise TypeError(f"{name} must be a contiguous CUDA float32 (batch, {cols}) tensor")
+    return t.data_ptr()
+
+
+def mlp_train_step(feats: torch.Tensor, labels: torch.Tensor, lr: float, stream=None) -> float:
+    loss = ctypes.c_float(0.0)
+    _check(lib().zf_mlp_train_step(_f32dev(feats, 8, "feats"), _f32dev(labels, 3, "labels"),
+                                   feats.shape[0], lr, ctypes.byref(loss), _stream(stream)))
+    return loss.value
+
+
+def mlp_grad(feats: torch.Tensor, labels: torch.Tensor, stream=None):
+    import numpy as np
+    g = np.empty(N_PARAMS, dtype=np.float32)
+    loss = ctypes.c_float(0.0)
+    _check(lib().zf_mlp_grad(_f32dev(feats, 8, "feats"), _f32dev(labels, 3, "labels"),
+                             feats.shape[0], g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                             ctypes.byref(loss), _stream(stream)))
+    return g, loss.value
+
+
+def mlp_predict(feat: torch.Tensor, stream=None):
+    if feat.dtype != torch.float32 or not feat.is_cuda or feat.numel() != 8:
+        raise TypeError("feat must be 8 CUDA float32 values")
+    c = (ctypes.c_double * 3)()
+    _check(lib().zf_mlp_predict(feat.data_ptr(), c, _stream(stream)))
+    return [c[0], c[1], c[2]]
