@@ -62,31 +62,40 @@ __global__ void __launch_bounds__(WM* WN * 64, 2)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-int num_tiles(int M, int N, bool sym) {
-  const int tm = M / kTile, tn = N / kTile;
-  return sym ? tm * (tm + 1) / 2 : tm * tn;
-}
-
 static bool dims_ok(int M, int N, int K, bool sym) {
   return M > 0 && N > 0 && K > 0 && M % kTile == 0 && N % kTile == 0 && K % kTile == 0 &&
          (!sym || M == N);
 }
 
-// Tile edge for the (h)(h)+(h)(l)+(l)(h) kernel: 256 (8 waves) when both output
-// dimensions allow it, else 128 (4 waves).  ZF_X3_TILE / ZF_X3_SYM_TILE = 128 or
-// 256 override the choice for plain / symmetric launches (tuning only).
-int x3_tile_edge(int M, int N, bool sym) {
-  const char* env = getenv(sym ? "ZF_X3_SYM_TILE" : "ZF_X3_TILE");
-  const int want = env ? atoi(env) : 256;
-  if (want == 256 && M % 256 == 0 && N % 256 == 0) return 256;
-  return 128;
-}
-
-int x3_blocks(int M, int N, bool sym) {
-  const int t = x3_tile_edge(M, N, sym);
+static int grid_blocks(int M, int N, int t, bool sym) {
   const int tm = M / t, tn = N / t;
   return sym ? tm * (tm + 1) / 2 : tm * tn;
 }
+
+// Tile edge of a launch: the largest of 256 / 128 / 64 that divides both output
+// dimensions and still yields at least 128 workgroups (half of the 256 CUs; fewer,
+// larger tiles beat more, smaller ones down to that point).  ZF_X3_TILE /
+// ZF_X3_SYM_TILE (64, 128 or 256) force the BF16x3 edge when it divides (tuning).
+int x3_tile_edge(int M, int N, bool sym) {
+  const char* env = getenv(sym ? "ZF_X3_SYM_TILE" : "ZF_X3_TILE");
+  if (env) {
+    const int want = atoi(env);
+    if ((want == 64 || want == 128 || want == 256) && M % want == 0 && N % want == 0) return want;
+  }
+  if (M % 256 == 0 && N % 256 == 0 && grid_blocks(M, N, 256, sym) >= 128) return 256;
+  if (grid_blocks(M, N, 128, sym) >= 128) return 128;
+  return 64;
+}
+
+int x3_blocks(int M, int N, bool sym) { return grid_blocks(M, N, x3_tile_edge(M, N, sym), sym); }
+
+int f64_tile_edge(int M, int N, bool sym) {
+  return grid_blocks(M, N, 128, sym) >= 128 ? 128 : 64;
+}
+
+int f64_blocks(int M, int N, bool sym) { return grid_blocks(M, N, f64_tile_edge(M, N, sym), sym); }
+
+int max_blocks(int M, int N) { return grid_blocks(M, N, 64, false); }
 
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
@@ -98,8 +107,12 @@ hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bh
     constexpr int BM = 256, BN = 256, BK = 32, WM = 2, WN = 4;
     hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
                        st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym ? 1 : 0, ep);
-  } else {
+  } else if (tile == 128) {
     constexpr int BM = 128, BN = 128, BK = 32, WM = 2, WN = 2;
+    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
+                       st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym ? 1 : 0, ep);
+  } else {
+    constexpr int BM = 64, BN = 64, BK = 32, WM = 2, WN = 2;
     hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
                        st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym ? 1 : 0, ep);
   }
@@ -109,11 +122,16 @@ hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bh
 hipError_t launch_gemm_f64(const double* A, int lda, const double* B, int ldb, int M, int N, int K,
                            bool sym, const EpiParams& ep, hipStream_t st) {
   if (!dims_ok(M, N, K, sym)) return hipErrorInvalidValue;
-  constexpr int BM = 128, BN = 128, BK = 16, WM = 2, WN = 2;
-  static_assert(BM == kTile && BN == kTile, "padding granule");
-  const int blocks = num_tiles(M, N, sym);
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0, st,
-                     A, lda, B, ldb, K, N / BN, sym ? 1 : 0, ep);
+  const int blocks = f64_blocks(M, N, sym);
+  if (f64_tile_edge(M, N, sym) == 128) {
+    constexpr int BM = 128, BN = 128, BK = 16, WM = 2, WN = 2;
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
+                       st, A, lda, B, ldb, K, N / BN, sym ? 1 : 0, ep);
+  } else {
+    constexpr int BM = 64, BN = 64, BK = 16, WM = 2, WN = 2;
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
+                       st, A, lda, B, ldb, K, N / BN, sym ? 1 : 0, ep);
+  }
   return hipGetLastError();
 }
 

@@ -41,39 +41,67 @@ static_assert(NPARAM == 4931, "parameter layout");
 // ---------------------------------------------------------------------------
 // Gershgorin statistics and tr(S): out[0] = max r_i, out[1] = min (S_ii - (r_i - |S_ii|)),
 // out[2] = mean r_i, out[3] = tr(S).  S: n x n, ld n.
-__global__ void gersh_stats_kernel(const double* __restrict__ S, int n, double* out) {
-  __shared__ double smax[256], smin[256], ssum[256], str[256];
+// Gershgorin statistics of S (n x n, ld n) in two passes: one wave per row (coalesced
+// row sums, a fixed-order shuffle tree), per-block partials {max r_i, min lo_i,
+// sum r_i, sum S_ii}, then one thread folds the partials in block order, so the result
+// depends on n only (deterministic).  lo_i = S_ii - (r_i - |S_ii|).
+constexpr int kGershBlocks = 512;
+
+__global__ void __launch_bounds__(256) gersh_rows_kernel(const double* __restrict__ S, int n,
+                                                         double* __restrict__ part) {
+  __shared__ double red[4][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double mx = 0.0, mn = 1e300, sm = 0.0, tr = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  for (int i = blockIdx.x * 4 + wave; i < n; i += gridDim.x * 4) {
     const double* row = S + (size_t)i * n;
     double r = 0.0;
-    for (int j = 0; j < n; ++j) r += fabs(row[j]);
+    for (int j = lane; j < n; j += 64) r += fabs(row[j]);
+    for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
     const double d = row[i];
     mx = fmax(mx, r);
     mn = fmin(mn, d - (r - fabs(d)));
     sm += r;
     tr += d;
   }
-  smax[threadIdx.x] = mx;
-  smin[threadIdx.x] = mn;
-  ssum[threadIdx.x] = sm;
-  str[threadIdx.x] = tr;
+  if (lane == 0) {
+    red[wave][0] = mx;
+    red[wave][1] = mn;
+    red[wave][2] = sm;
+    red[wave][3] = tr;
+  }
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
-      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
-      ssum[threadIdx.x] += ssum[threadIdx.x + w];
-      str[threadIdx.x] += str[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    out[0] = smax[0];
-    out[1] = smin[0];
-    out[2] = ssum[0] / n;
-    out[3] = str[0];
+    for (int w = 1; w < 4; ++w) {
+      red[0][0] = fmax(red[0][0], red[w][0]);
+      red[0][1] = fmin(red[0][1], red[w][1]);
+      red[0][2] += red[w][2];
+      red[0][3] += red[w][3];
+    }
+    for (int k = 0; k < 4; ++k) part[(size_t)blockIdx.x * 4 + k] = red[0][k];
   }
+}
+
+__global__ void gersh_final_kernel(const double* __restrict__ part, int blocks, int n,
+                                   double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double mx = part[0], mn = part[1], sm = part[2], tr = part[3];
+  for (int b = 1; b < blocks; ++b) {
+    mx = fmax(mx, part[4 * b]);
+    mn = fmin(mn, part[4 * b + 1]);
+    sm += part[4 * b + 2];
+    tr += part[4 * b + 3];
+  }
+  out[0] = mx;
+  out[1] = mn;
+  out[2] = sm / n;
+  out[3] = tr;
+}
+
+static void launch_gersh(const double* S, int n, double* out, double* part, hipStream_t st) {
+  const int rows4 = (n + 3) / 4;
+  const int blocks = rows4 < kGershBlocks ? rows4 : kGershBlocks;
+  hipLaunchKernelGGL(gersh_rows_kernel, dim3(blocks), dim3(256), 0, st, S, n, part);
+  hipLaunchKernelGGL(gersh_final_kernel, dim3(1), dim3(64), 0, st, part, blocks, n, out);
 }
 
 // Up to 8 Frobenius inner products <A_k, B_k> over the valid n x n block of np x np
@@ -293,7 +321,7 @@ __global__ void guess_write_kernel(const double* __restrict__ S, int n, const do
 // host helpers used by zf_api.hip
 // ---------------------------------------------------------------------------
 // features from S (n x n, ld n) and S^2 (np x np: FP64 S2 or FP32 S2f); writes 8 floats
-// to feats (device) and {g, g_lo} to gstats (device, 2 doubles).  scratch: >= 4096 doubles.
+// to feats (device); scratch (>= 6656 doubles) starts with {g, g_lo, mean r_i, tr S}.
 int guess_features(const double* S, int n, const double* S2, const float* S2f, int np,
                    const double* S64pad, float* feats, double* scratch, hipStream_t st);
 
@@ -339,8 +367,9 @@ __global__ void feat_dots_partial_kernel(const double* __restrict__ S, const dou
 
 int guess_features(const double* S, int n, const double* S2, const float* S2f, int np,
                    const double* S64pad, float* feats, double* scratch, hipStream_t st) {
-  // scratch: [0..3] Gershgorin statistics and tr(S), [8..15] dots, [16..16+8*512) partials
-  hipLaunchKernelGGL(gersh_stats_kernel, dim3(1), dim3(256), 0, st, S, n, scratch);
+  // scratch: [0..3] Gershgorin statistics and tr(S), [8..15] dots, [16..16+8*512) dot
+  // partials, [4608..4608+4*512) Gershgorin partials
+  launch_gersh(S, n, scratch, scratch + 4608, st);
   const int blocks = n < 512 ? n : 512;
   hipLaunchKernelGGL(feat_dots_partial_kernel, dim3(blocks), dim3(256), 0, st, S64pad, S2, S2f, n,
                      np, scratch + 16);
@@ -429,8 +458,8 @@ int dots8(const double* const* a, const double* const* b, int count, int n, int 
   return 0;
 }
 
-int gersh_stats(const double* S, int n, double* out_dev, hipStream_t st) {
-  hipLaunchKernelGGL(gersh_stats_kernel, dim3(1), dim3(256), 0, st, S, n, out_dev);
+int gersh_stats(const double* S, int n, double* out_dev, double* part, hipStream_t st) {
+  launch_gersh(S, n, out_dev, part, st);
   GHIP_TRY(hipGetLastError());
   return 0;
 }

@@ -177,7 +177,7 @@ static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out) {
     w.device = dev;
     w.np = np_new;
     const size_t m = (size_t)np_new * np_new;
-    const int tiles = num_tiles(np_new, np_new, false);
+    const int tiles = max_blocks(np_new, np_new);
     w.has_x3 = need_x3 || keep_x3;
     w.has_f64 = need_f64 || keep_f64;
     ZF_TRY(ws_alloc(w, &w.partials, tiles));
@@ -269,7 +269,8 @@ static int gemm_f64(const double* A, const double* B, int np, bool sym, const Ep
     pe.a = take_event();
     pe.b = take_event();
     pe.cls = sym ? K_F64_SYM : K_F64;
-    pe.flops = 2.0 * (double)num_tiles(np, np, sym) * kTile * kTile * (double)np;
+    const double t = (double)f64_tile_edge(np, np, sym);
+    pe.flops = 2.0 * (double)f64_blocks(np, np, sym) * t * t * (double)np;
     HIP_TRY(hipEventRecord(pe.a, st));
   }
   HIP_TRY(launch_gemm_f64(A, np, B, np, np, np, np, sym, ep, st));
@@ -336,7 +337,7 @@ static int delta_eval(Ctx& c, bool high, bool want_split, int cur, double* err) 
     e2.partials = w.partials;
     ZF_TRY(gemm_f64(w.z64c[cur], w.a64t, np, true, e2, c.st));
   }
-  return fetch_err(c, high ? num_tiles(np, np, true) : x3_blocks(np, np, true), err);
+  return fetch_err(c, high ? f64_blocks(np, np, true) : x3_blocks(np, np, true), err);
 }
 
 // Q = sum_{k=1..m} c_k delta^k by Horner over symmetric GEMMs (m >= 2).
@@ -767,7 +768,7 @@ int zf_guess_label(const double* S, const double* Z, int n, double* c, void* str
   ZF_TRY(gemm_f64(w->a64t, w->s64, np, true, e3, st));
   const double* a[7] = {w->s64, w->s64, w->a64t, w->a64t, w->s64, w->a64t, w->d64};
   const double* b[7] = {w->s64, w->a64t, w->a64t, w->d64, w->z64r[0], w->z64r[0], w->z64r[0]};
-  ZF_TRY(gersh_stats(S, n, w->gscr, st));
+  ZF_TRY(gersh_stats(S, n, w->gscr, w->gscr + 4608, st));
   ZF_TRY(dots8(a, b, 7, n, np, w->gscr + 8, w->gscr + 16, st));
   double hv[16];
   HIP_TRY(hipMemcpyAsync(hv, w->gscr, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -826,7 +827,7 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
   double *a64, *b64, *c64, *d64 = nullptr, *part;
   int rc = 0;
   if ((rc = alloc(e * 8, (void**)&a64)) || (rc = alloc(e * 8, (void**)&b64)) ||
-      (rc = alloc(e * 8, (void**)&c64)) || (rc = alloc(num_tiles(np, np, false) * 8, (void**)&part)) ||
+      (rc = alloc(e * 8, (void**)&c64)) || (rc = alloc(max_blocks(np, np) * 8, (void**)&part)) ||
       (D && (rc = alloc(e * 8, (void**)&d64)))) {
     cleanup();
     return rc;
@@ -870,7 +871,7 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
       cleanup();
       return rc;
     }
-    he = launch_norm_finalize(part, precision == ZF_BF16X3 ? x3_blocks(np, np, sym != 0) : num_tiles(np, np, sym != 0), nrm, st);
+    he = launch_norm_finalize(part, precision == ZF_BF16X3 ? x3_blocks(np, np, sym != 0) : f64_blocks(np, np, sym != 0), nrm, st);
   }
   if (he == hipSuccess)
     he = hipMemcpy2DAsync(C, (size_t)nn * 8, c64, (size_t)np * 8, (size_t)nn * 8, m,

@@ -73,9 +73,11 @@ struct EpiParams {
 // Launchers (return hipSuccess or the launch error).  All dimensions must be
 // multiples of kTile; the caller pads.  Symmetric mode requires M == N.
 constexpr int kTile = 128;
-int num_tiles(int M, int N, bool sym);   // blocks of the FP64 kernel (kTile tiles)
 int x3_tile_edge(int M, int N, bool sym);  // tile edge the BF16x3 launch will use
 int x3_blocks(int M, int N, bool sym);   // blocks (= norm partials) of that launch
+int f64_tile_edge(int M, int N, bool sym);
+int f64_blocks(int M, int N, bool sym);
+int max_blocks(int M, int N);            // upper bound of the above (smallest tile edge)
 
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
@@ -120,6 +122,6 @@ hipError_t launch_guess_write(const double* S, int n, const double* S2, const fl
                               u16* zr_lo, u16* zc_hi, u16* zc_lo, hipStream_t st);
 int dots8(const double* const* a, const double* const* b, int count, int n, int np, double* out_dev,
           double* partial, hipStream_t st);
-int gersh_stats(const double* S, int n, double* out_dev, hipStream_t st);
+int gersh_stats(const double* S, int n, double* out_dev, double* part, hipStream_t st);
 
 }  // namespace zf

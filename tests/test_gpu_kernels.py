@@ -72,8 +72,9 @@ def test_split_empty(zf):
 SHAPES = [(128, 128, 128), (200, 200, 300), (96, 260, 70), (1, 1, 1), (384, 256, 513), (640, 640, 384)]
 
 
-@pytest.mark.parametrize("m,nn,k", SHAPES)
+@pytest.mark.parametrize("m,nn,k", SHAPES + [(1536, 1536, 256)])
 def test_gemm_f64(zf, m, nn, k):
+    """Small outputs take 64-wide tiles, 1536^2 and up 128-wide ones."""
     rng = np.random.default_rng(m * 7 + nn + k)
     A = rng.standard_normal((m, k))
     B = rng.standard_normal((nn, k))
@@ -83,7 +84,7 @@ def test_gemm_f64(zf, m, nn, k):
     assert np.all(np.abs(C.cpu().numpy() - ref) <= bound)
 
 
-@pytest.mark.parametrize("tile", ["128", "256"])
+@pytest.mark.parametrize("tile", ["64", "128", "256"])
 @pytest.mark.parametrize("m,nn,k", SHAPES)
 def test_gemm_bf16x3(zf, m, nn, k, tile, monkeypatch):
     monkeypatch.setenv("ZF_X3_TILE", tile)
@@ -102,8 +103,9 @@ def test_gemm_bf16x3(zf, m, nn, k, tile, monkeypatch):
     assert np.all(np.abs(C - exact) <= (3 * u * u + 3 * k * U32) * (np.abs(A) @ np.abs(B).T) * 1.01)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "bf16x3-t128"])
-@pytest.mark.parametrize("n,k", [(128, 128), (300, 200), (640, 512), (129, 64), (1000, 256)])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "bf16x3-t128", "bf16x3-t64"])
+@pytest.mark.parametrize("n,k", [(128, 128), (300, 200), (640, 512), (129, 64), (1000, 256),
+                                 (2048, 128)])
 def test_gemm_symmetric_delta_epilogue(zf, prec, n, k, monkeypatch):
     """delta = I - A M A^T (symmetric product) in symmetric mode: only tiles on or
     above the diagonal are computed; the result is mirrored exactly and the norm
@@ -113,9 +115,9 @@ def test_gemm_symmetric_delta_epilogue(zf, prec, n, k, monkeypatch):
     M = rng.standard_normal((k, k))
     M = (M + M.T) / 2
     B = A @ M                     # A B^T = A M A^T is symmetric
-    if prec.endswith("-t128"):
-        monkeypatch.setenv("ZF_X3_SYM_TILE", "128")
-        prec = prec[:-5]
+    if "-t" in prec:
+        prec, tile = prec.split("-t")
+        monkeypatch.setenv("ZF_X3_SYM_TILE", tile)
     C, nsq = zf.t_gemm(prec, _cuda(A), _cuda(B), sym=True, beta=-1.0, gamma=1.0)
     C = C.cpu().numpy()
     assert np.array_equal(C, C.T)
