@@ -66,6 +66,13 @@ enum zf_stop {
   ZF_STOP_MONOTONE = 1  /* stop at n > 0 once Err_n >= Err_{n-1}                    */
 };
 
+/* The initial guess a run started from (zf_result.z0_used). */
+enum zf_z0_kind {
+  ZF_Z0_GIVEN = 0,           /* the caller's Z0                                        */
+  ZF_Z0_SCALED_IDENTITY = 1, /* I / sqrt(g), g = max_i sum_j |S_ij| (Gershgorin bound)  */
+  ZF_Z0_LEARNED = 2          /* (c0 I + c1 S/g + c2 (S/g)^2) / sqrt(g) from the network  */
+};
+
 /* Refinement phase after a low-precision stop (Sec. IV.B, Algorithm 3). */
 enum zf_refine_mode {
   ZF_REFINE_OFF = 0,       /* return the low-precision result                        */
@@ -94,7 +101,7 @@ typedef struct {
                       FP64 evaluation ran, else the low-precision value)               */
   double final_rms;/* final_err / sqrt(n)                                              */
   int status;      /* 0, or the ZF_ERR_* code of this matrix (batched calls report each)  */
-  int z0_used;     /* 0 given, 1 scaled identity, 2 learned                               */
+  int z0_used;     /* enum zf_z0_kind                                                     */
 } zf_result;
 
 /* Fill *opts with the defaults: order 2, ZF_BF16X3, ZF_STOP_RATIO, 100 sweeps,
@@ -127,10 +134,13 @@ int zf_refine_ex(const double* S, const double* Z0, int n, const zf_opts* opts, 
 
 /*
  * zf_refine_batched -- refine count independent matrices of uneven order together.
+ *   count       1..65535 matrices.
  *   S[m], Z[m]  device pointers (host arrays of count pointers), n[m] x n[m] FP64, n[m] in
  *               1..8192; Z0 may be NULL (all scaled identity) or hold NULL entries.
  *   opts        order must be 2, precision ZF_BF16X3, refine ZF_REFINE_OFF or
- *               ZF_REFINE_F64_DELTA (opts NULL = defaults).
+ *               ZF_REFINE_F64_DELTA (opts NULL = defaults).  opts.z0 = 1 gives every
+ *               matrix without a Z0 the learned guess (per-matrix acceptance on the
+ *               device, scaled-identity fallback flagged in its result).
  *   res         host[count] or NULL: per-matrix result including status.
  *   hist        host[count * hist_cap]: matrix m's residual history at m * hist_cap.
  * Every matrix runs the recursion and stop test of zf_refine_ex; the matrices advance
@@ -185,6 +195,13 @@ int zf_mlp_set_params(const float* host_params, int count);  /* count must be 49
 int zf_mlp_get_params(float* host_params, int count);
 /* standardization: x' = (x - mu_x) / sd_x (8 each), y = y' sd_y + mu_y (3 each) */
 int zf_mlp_set_norm(const float* mu_x, const float* sd_x, const float* mu_y, const float* sd_y);
+/* zf_mlp_save / zf_mlp_load -- the loaded network (normalization and parameters) to / from
+ * a file at path (host string): magic "ZFMLP\0\0\1", int32 {8, 64, 3, 4931}, float32
+ * mu_x[8], sd_x[8], mu_y[3], sd_y[3], float32 parameters[4931], little-endian.  Save
+ * needs a loaded network; load validates the magic, shape, size and finiteness and
+ * leaves the current network untouched on any error (ZF_ERR_ARG). */
+int zf_mlp_save(const char* path);
+int zf_mlp_load(const char* path);
 /* one Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error of the standardized
  * labels; feats (batch x 8) and labels (batch x 3, raw c) are device FP32; loss (host) may
  * be NULL (then the call does not synchronize). */

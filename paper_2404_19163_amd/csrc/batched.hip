@@ -19,6 +19,10 @@
 // and replayed until every matrix is done.  The tile edge of each matrix (64 or
 // 128) comes from a table indexed by its order, filled by zf_batched_autotune or
 // left at its defaults.
+//
+// Set-up (once, before the graph): split S; for matrices taking the learned guess
+// the grouped BF16x3 S^2 (stage S2), then per-matrix statistics and features, one
+// network inference per matrix and the acceptance test on the device; Z0 last.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -44,7 +48,7 @@ namespace zf {
 
 enum { PH_LOW = 0, PH_HIGH = 1 };
 enum { ACT_EVAL = 0, ACT_UPDATE = 1, ACT_TRANSITION = 2, ACT_DONE = 3 };
-enum { OP_L1 = 0, OP_L2, OP_H1, OP_H2, OP_U3, OP_U4 };
+enum { OP_L1 = 0, OP_L2, OP_H1, OP_H2, OP_U3, OP_U4, OP_S2 };
 
 // Per-matrix record: buffers (carved from one arena) and the device-side state of
 // the recursion.  Only the DECIDE kernel writes the state.
@@ -53,6 +57,7 @@ struct BMat {
   long long pbase;  // first norm partial of this matrix
   int phase, action, it, cur, src;
   int upd_l, upd_h, evals_l, evals_h, flags, status, hist_len;
+  int learn, z0_used;  // learned guess requested; guess taken (ZF_Z0_*)
   double prev, err_l, err_h;
   double* hist;
   u16 *s_hi, *s_lo, *zr_hi[2], *zr_lo[2], *zc_hi[2], *zc_lo[2];
@@ -76,8 +81,11 @@ using F64_128 = F64Cfg<128, 128, 16, 2, 2>;
 static_assert(X3_64::NT == 256 && X3_128::NT == 256 && F64_64::NT == 256 && F64_128::NT == 256,
               "grouped kernels run every tile body with one 256-thread block");
 
-__device__ __forceinline__ bool op_applies(int op, int phase, int action) {
+__device__ __forceinline__ bool op_applies(int op, const BMat& M) {
+  const int phase = M.phase, action = M.action;
   switch (op) {
+    case OP_S2:
+      return M.learn != 0;
     case OP_L1:
     case OP_L2:
       return phase == PH_LOW && action != ACT_DONE;
@@ -97,7 +105,7 @@ __global__ void __launch_bounds__(256, 2)
   for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const TileTask tk = tasks[t];
     const BMat& M = mats[tk.m];
-    if (!op_applies(op, M.phase, M.action)) continue;
+    if (!op_applies(op, M)) continue;
     const int np = M.np, T = M.tile;
     EpiParams ep;
     memset(&ep, 0, sizeof ep);
@@ -123,6 +131,10 @@ __global__ void __launch_bounds__(256, 2)
       ep.ohi = ep.othi = M.d_hi;
       ep.olo = ep.otlo = M.d_lo;
       ep.partials = partials + M.pbase;
+    } else if (op == OP_S2) {  // S^2 (symmetric) into the second FP32 master
+      ah = bh = M.s_hi;
+      al = bl = M.s_lo;
+      ep.o32 = ep.ot32 = M.z32[1];
     } else if (op == OP_U3) {
       ah = bh = M.d_hi;
       al = bl = M.d_lo;
@@ -154,7 +166,7 @@ __global__ void __launch_bounds__(256, 2)
         ep.otlo = M.zc_lo[M.cur];
       }
     }
-    const bool sym = (op == OP_L2 || op == OP_U3);
+    const bool sym = (op == OP_L2 || op == OP_U3 || op == OP_S2);
     if (sym) {
       mode = (tk.ti == tk.tj) ? 2 : 1;
       // index of (ti, tj) in the row-major upper triangle of a T x T tile grid
@@ -179,7 +191,7 @@ __global__ void __launch_bounds__(256, 2)
   for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const TileTask tk = tasks[t];
     const BMat& M = mats[tk.m];
-    if (!op_applies(op, M.phase, M.action)) continue;
+    if (!op_applies(op, M)) continue;
     const int np = M.np, T = M.tile;
     EpiParams ep;
     memset(&ep, 0, sizeof ep);
@@ -287,29 +299,32 @@ __global__ void decide_kernel(BMat* mats, int count, const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// element-wise batched kernels: a flat index over sum_m rows_m * cols_m, the matrix
-// found by binary search over the prefix offsets
+// element-wise batched kernels: grid (tiles, count); block (x, m) handles the 64 x 64
+// tile x of matrix m's padded np x np layout (row-major tile order) and exits at
+// once when m has fewer tiles or is not in the kernel's stage.  Transposed copies
+// go through a padded LDS tile so that both layouts are written coalesced.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int find_matrix(const long long* __restrict__ off, int count, long long e) {
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= e) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
+constexpr int kET = 64;  // element-wise tile edge (np is a multiple of it)
+
+__device__ __forceinline__ bool tile_of(const BMat& M, int& i0, int& j0) {
+  const int T = M.np / kET;
+  if ((int)blockIdx.x >= T * T) return false;
+  i0 = ((int)blockIdx.x / T) * kET;
+  j0 = ((int)blockIdx.x % T) * kET;
+  return true;
 }
 
 // S_m (n x n) -> BF16 pair and (optionally) FP64 copy, zero-padded to np x np
-__global__ void b_split_kernel(const BMat* __restrict__ mats, int count, const double* const* S,
-                               const long long* __restrict__ off, long long total, int with64) {
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int m = find_matrix(off, count, e);
-    const BMat& M = mats[m];
-    const long long le = e - off[m];
-    const int i = (int)(le / M.np), j = (int)(le % M.np);
-    const double a = (i < M.n && j < M.n) ? S[m][(size_t)i * M.n + j] : 0.0;
+__global__ void __launch_bounds__(256) b_split_kernel(const BMat* __restrict__ mats,
+                                                      const double* const* S, int with64) {
+  const BMat& M = mats[blockIdx.y];
+  int i0, j0;
+  if (!tile_of(M, i0, j0)) return;
+  const double* Sm = S[blockIdx.y];
+  for (int e = threadIdx.x; e < kET * kET; e += 256) {
+    const int i = i0 + e / kET, j = j0 + e % kET;
+    const double a = (i < M.n && j < M.n) ? Sm[(size_t)i * M.n + j] : 0.0;
+    const size_t le = (size_t)i * M.np + j;
     u16 h, l;
     split_bf16((float)a, h, l);
     M.s_hi[le] = h;
@@ -318,79 +333,190 @@ __global__ void b_split_kernel(const BMat* __restrict__ mats, int count, const d
   }
 }
 
-// Gershgorin bound per matrix (one block per matrix)
-__global__ void b_gersh_kernel(const BMat* __restrict__ mats, const double* const* S, double* g) {
+// Per-matrix statistics, one block of 4 waves per matrix, one wave per row:
+// stats[4m..] = {g = max r_i, g_lo = min (S_ii - (r_i - |S_ii|)), mean r_i, tr S},
+// r_i = sum_j |S_ij|.  Matrices taking the learned guess also get the Frobenius
+// products ||S||^2, <S, S^2>, ||S^2||^2 (S^2 from stage S2, FP32 in z32[1]) and
+// their 8 features.  Fixed-order reductions: repeatable bit for bit.
+__global__ void __launch_bounds__(256) b_stats_kernel(const BMat* __restrict__ mats,
+                                                      const double* const* S, double* g,
+                                                      double* stats, float* feats) {
   const int m = blockIdx.x;
   const BMat& M = mats[m];
-  __shared__ double red[256];
-  double mx = 0.0;
-  for (int i = threadIdx.x; i < M.n; i += blockDim.x) {
-    const double* row = S[m] + (size_t)i * M.n;
-    double s = 0.0;
-    for (int j = 0; j < M.n; ++j) s += fabs(row[j]);
-    mx = fmax(mx, s);
+  const int n = M.n, np = M.np;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double* Sm = S[m];
+  const float* S2 = M.z32[1];
+  const bool learn = M.learn != 0;
+  __shared__ double red[4][7];
+  double mx = 0.0, mn = 1e300, sm = 0.0, tr = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int i = wave; i < n; i += 4) {
+    const double* row = Sm + (size_t)i * n;
+    double r = 0.0;
+    for (int j = lane; j < n; j += 64) {
+      const double v = row[j];
+      r += fabs(v);
+      if (learn) {
+        const double q = (double)S2[(size_t)i * np + j];
+        a0 += v * v;
+        a1 += v * q;
+        a2 += q * q;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+    const double d = row[i];
+    mx = fmax(mx, r);
+    mn = fmin(mn, d - (r - fabs(d)));
+    sm += r;
+    tr += d;
   }
-  red[threadIdx.x] = mx;
+  for (int o = 32; o > 0; o >>= 1) {
+    a0 += __shfl_xor(a0, o, 64);
+    a1 += __shfl_xor(a1, o, 64);
+    a2 += __shfl_xor(a2, o, 64);
+  }
+  if (lane == 0) {
+    red[wave][0] = mx;
+    red[wave][1] = mn;
+    red[wave][2] = sm;
+    red[wave][3] = tr;
+    red[wave][4] = a0;
+    red[wave][5] = a1;
+    red[wave][6] = a2;
+  }
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      red[0][0] = fmax(red[0][0], red[w][0]);
+      red[0][1] = fmin(red[0][1], red[w][1]);
+      for (int k = 2; k < 7; ++k) red[0][k] += red[w][k];
+    }
+    const double gg = red[0][0];
+    g[m] = gg;
+    stats[4 * m + 0] = gg;
+    stats[4 * m + 1] = red[0][1];
+    stats[4 * m + 2] = red[0][2] / n;
+    stats[4 * m + 3] = red[0][3];
+    float* f = feats + 8 * (size_t)m;
+    if (learn)
+      finish_features(gg, red[0][1], red[0][2] / n, red[0][3], red[0][4], red[0][5], red[0][6], n, f);
+    else
+      for (int k = 0; k < 8; ++k) f[k] = 0.f;
   }
-  if (threadIdx.x == 0) g[m] = red[0];
 }
 
-// Z0 (given, or I / sqrt(g)) into Z32, Zr and Zc of buffer 0
-__global__ void b_init_kernel(const BMat* __restrict__ mats, int count, const double* const* Z0,
-                              const double* __restrict__ g, const long long* __restrict__ off,
-                              long long total) {
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int m = find_matrix(off, count, e);
-    const BMat& M = mats[m];
-    const long long le = e - off[m];
-    const int i = (int)(le / M.np), j = (int)(le % M.np);
-    double v;
-    if (Z0[m]) v = (i < M.n && j < M.n) ? Z0[m][(size_t)i * M.n + j] : 0.0;
-    else v = (i == j && i < M.n) ? 1.0 / sqrt(g[m]) : 0.0;
+// Acceptance of the predicted coefficients (one thread per matrix); on success
+// coef[4m + 3] = g and the guess is marked learned, else the scaled identity with
+// ZF_WARN_Z0_FALLBACK.
+__global__ void b_accept_kernel(BMat* mats, int count, const double* __restrict__ stats,
+                                double* coef) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= count) return;
+  BMat& M = mats[m];
+  if (!M.learn) return;
+  double c[3] = {coef[4 * m], coef[4 * m + 1], coef[4 * m + 2]};
+  const double g = stats[4 * m], glo = stats[4 * m + 1];
+  bool ok = (g > 0.0) && isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]);
+  if (ok) ok = accept_poly(c, glo > 0.0 ? glo / g : 0.0);
+  if (ok) {
+    coef[4 * m] = c[0];
+    coef[4 * m + 1] = c[1];
+    coef[4 * m + 2] = c[2];
+    coef[4 * m + 3] = g;
+    M.z0_used = ZF_Z0_LEARNED;
+  } else {
+    M.z0_used = ZF_Z0_SCALED_IDENTITY;
+    M.flags |= ZF_WARN_Z0_FALLBACK;
+  }
+}
+
+// Z0 into Z32, Zr and Zc of buffer 0: given, learned (c0 I + c1 S/g + c2 (S/g)^2) /
+// sqrt(g) with S^2 from z32[1], or I / sqrt(g)
+__global__ void __launch_bounds__(256) b_init_kernel(const BMat* __restrict__ mats,
+                                                     const double* const* Z0, const double* const* S,
+                                                     const double* __restrict__ g,
+                                                     const double* __restrict__ coef) {
+  __shared__ u16 th[kET][kET + 1], tl[kET][kET + 1];
+  const int m = blockIdx.y;
+  const BMat& M = mats[m];
+  int i0, j0;
+  if (!tile_of(M, i0, j0)) return;
+  const int n = M.n, np = M.np;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (M.z0_used == ZF_Z0_LEARNED) {
+    const double* cg = coef + 4 * (size_t)m;
+    const double gg = cg[3], sg = 1.0 / sqrt(gg);
+    a0 = cg[0] * sg;
+    a1 = cg[1] * sg / gg;
+    a2 = cg[2] * sg / (gg * gg);
+  } else if (M.z0_used == ZF_Z0_SCALED_IDENTITY) {
+    a0 = 1.0 / sqrt(g[m]);
+  }
+  for (int e = threadIdx.x; e < kET * kET; e += 256) {
+    const int r = e / kET, c = e % kET;
+    const int i = i0 + r, j = j0 + c;
+    const size_t le = (size_t)i * np + j;
+    double v = 0.0;
+    if (i < n && j < n) {
+      if (M.z0_used == ZF_Z0_GIVEN)
+        v = Z0[m][(size_t)i * n + j];
+      else if (M.z0_used == ZF_Z0_LEARNED)
+        v = a1 * S[m][(size_t)i * n + j] + a2 * (double)M.z32[1][le] + (i == j ? a0 : 0.0);
+      else
+        v = (i == j) ? a0 : 0.0;
+    }
     const float f = (float)v;
     u16 h, l;
     split_bf16(f, h, l);
-    const size_t t = (size_t)j * M.np + i;
     M.z32[0][le] = f;
     M.zr_hi[0][le] = h;
     M.zr_lo[0][le] = l;
-    M.zc_hi[0][t] = h;
-    M.zc_lo[0][t] = l;
+    th[r][c] = h;
+    tl[r][c] = l;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kET * kET; e += 256) {
+    const int r = e / kET, c = e % kET;  // transposed row j0 + r, column i0 + c
+    const size_t t = (size_t)(j0 + r) * np + i0 + c;
+    M.zc_hi[0][t] = th[c][r];
+    M.zc_lo[0][t] = tl[c][r];
   }
 }
 
 // FP32 master -> FP64 row-major and transposed for matrices entering the FP64 phase
-__global__ void b_widen_kernel(const BMat* __restrict__ mats, int count,
-                               const long long* __restrict__ off, long long total) {
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int m = find_matrix(off, count, e);
-    const BMat& M = mats[m];
-    if (M.action != ACT_TRANSITION) continue;
-    const long long le = e - off[m];
-    const int i = (int)(le / M.np), j = (int)(le % M.np);
-    const double v = (double)M.z32[M.cur][le];
-    M.z64r[M.cur][le] = v;
-    M.z64c[M.cur][(size_t)j * M.np + i] = v;
+__global__ void __launch_bounds__(256) b_widen_kernel(const BMat* __restrict__ mats) {
+  __shared__ float tv[kET][kET + 1];
+  const BMat& M = mats[blockIdx.y];
+  if (M.action != ACT_TRANSITION) return;
+  int i0, j0;
+  if (!tile_of(M, i0, j0)) return;
+  const int np = M.np, cur = M.cur;
+  for (int e = threadIdx.x; e < kET * kET; e += 256) {
+    const int r = e / kET, c = e % kET;
+    const size_t le = (size_t)(i0 + r) * np + j0 + c;
+    const float f = M.z32[cur][le];
+    M.z64r[cur][le] = (double)f;
+    tv[r][c] = f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kET * kET; e += 256) {
+    const int r = e / kET, c = e % kET;
+    M.z64c[cur][(size_t)(j0 + r) * np + i0 + c] = (double)tv[c][r];
   }
 }
 
 // unpadded result: FP64 iterate if the FP64 phase ran, else the FP32 master
-__global__ void b_output_kernel(const BMat* __restrict__ mats, int count, double* const* Z,
-                                const long long* __restrict__ off, long long total, int from64) {
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int m = find_matrix(off, count, e);
-    const BMat& M = mats[m];
-    const long long le = e - off[m];
-    const int i = (int)(le / M.n), j = (int)(le % M.n);
+__global__ void __launch_bounds__(256) b_output_kernel(const BMat* __restrict__ mats,
+                                                       double* const* Z, int from64) {
+  const BMat& M = mats[blockIdx.y];
+  int i0, j0;
+  if (!tile_of(M, i0, j0)) return;
+  double* Zm = Z[blockIdx.y];
+  for (int e = threadIdx.x; e < kET * kET; e += 256) {
+    const int i = i0 + e / kET, j = j0 + e % kET;
+    if (i >= M.n || j >= M.n) continue;
     const size_t src = (size_t)i * M.np + j;
-    Z[m][le] = from64 ? M.z64r[M.cur][src] : (double)M.z32[M.cur][src];
+    Zm[(size_t)i * M.n + j] = from64 ? M.z64r[M.cur][src] : (double)M.z32[M.cur][src];
   }
 }
 
@@ -451,16 +577,12 @@ static int grow(void** p, size_t* cap, size_t need) {
   return 0;
 }
 
-static int grid_for_total(long long total) {
-  long long g = (total + 255) / 256;
-  return (int)std::max(1LL, std::min(g, 65536LL));
-}
 
 struct Plan {
   std::vector<BMat> mats;
   std::vector<TileTask> full, sym;
-  std::vector<long long> off_pad, off_out;
-  long long total_pad = 0, total_out = 0, partials = 0;
+  long long partials = 0;
+  int max_etiles = 1;  // largest (np / 64)^2 of the batch: x extent of element-wise grids
   size_t arena = 0;
 };
 
@@ -478,10 +600,7 @@ static void make_plan(int count, const int* n, bool with64, Plan& P) {
     M.tiles_sym = T * (T + 1) / 2;
     M.pbase = P.partials;
     P.partials += M.tiles_sym;
-    P.off_pad.push_back(P.total_pad);
-    P.total_pad += (long long)M.np * M.np;
-    P.off_out.push_back(P.total_out);
-    P.total_out += (long long)M.n * M.n;
+    P.max_etiles = std::max(P.max_etiles, (M.np / kET) * (M.np / kET));
     const size_t e = (size_t)M.np * M.np;
     bytes += 16 * align256(e * 2) + 2 * align256(e * 4) + (with64 ? 7 * align256(e * 8) : 0);
   }
@@ -541,8 +660,7 @@ struct Launch {
   BMat* mats;
   TileTask *full, *sym;
   int nfull, nsym;
-  long long *off_pad;
-  long long total_pad;
+  int etiles;
   double* partials;
   int* remaining;
   int count, grid, order, rule, max_l, max_h, refine_on, hist_cap;
@@ -564,8 +682,7 @@ static hipError_t macro_sweep(const Launch& L, hipStream_t st) {
   hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, st, L.mats, L.count, L.partials, L.order,
                      L.rule, L.max_l, L.max_h, L.refine_on, L.hist_cap, L.remaining);
   if (L.refine_on)
-    hipLaunchKernelGGL(b_widen_kernel, dim3(grid_for_total(L.total_pad)), dim3(256), 0, st, L.mats,
-                       L.count, L.off_pad, L.total_pad);
+    hipLaunchKernelGGL(b_widen_kernel, dim3(L.etiles, L.count), dim3(256), 0, st, L.mats);
   hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(L.grid, L.nsym)), dim3(256), 0, st, L.sym,
                      L.nsym, L.mats, (int)OP_U3, L.c1, L.c2, L.partials);
   hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(L.grid, L.nfull)), dim3(256), 0, st, L.full,
@@ -576,7 +693,8 @@ static hipError_t macro_sweep(const Launch& L, hipStream_t st) {
 static int batched_impl(int count, const double* const* S, const double* const* Z0, const int* n,
                         const zf_opts& o, double* const* Z, zf_result* res, double* hist,
                         int hist_cap, hipStream_t st) {
-  if (count <= 0 || !S || !Z || !n) return set_error(ZF_ERR_ARG, "bad batch arguments");
+  if (count <= 0 || count > 65535 || !S || !Z || !n)
+    return set_error(ZF_ERR_ARG, "bad batch arguments (count must be in 1..65535)");
   if (o.order != 2) return set_error(ZF_ERR_ARG, "the batched path supports order 2 (got %d)", o.order);
   if (o.precision != ZF_BF16X3)
     return set_error(ZF_ERR_ARG, "the batched path runs ZF_BF16X3 (got %d)", o.precision);
@@ -585,6 +703,7 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   if (o.stop != ZF_STOP_RATIO && o.stop != ZF_STOP_MONOTONE)
     return set_error(ZF_ERR_ARG, "unknown stop rule %d", o.stop);
   if (hist_cap < 0 || (hist_cap > 0 && !hist)) return set_error(ZF_ERR_ARG, "bad hist buffer");
+  if (o.z0 != 0 && o.z0 != 1) return set_error(ZF_ERR_ARG, "unknown guess kind %d", o.z0);
   for (int m = 0; m < count; ++m) {
     if (n[m] <= 0 || n[m] > 8192)
       return set_error(ZF_ERR_ARG, "matrix %d: order %d outside 1..8192", m, n[m]);
@@ -606,25 +725,43 @@ static int batched_impl(int count, const double* const* S, const double* const* 
 
   Plan P;
   make_plan(count, n, with64, P);
+  // guesses: given where Z0[m] is set, else learned (opts.z0 = 1, network loaded; the
+  // device may still fall back) or the scaled identity
+  const bool have_net = net_ready();
+  int n_learn = 0;
+  for (int m = 0; m < count; ++m) {
+    BMat& M = P.mats[m];
+    if (Z0 && Z0[m]) {
+      M.z0_used = ZF_Z0_GIVEN;
+    } else if (o.z0 == 1 && have_net) {
+      M.learn = 1;
+      M.z0_used = ZF_Z0_LEARNED;
+      ++n_learn;
+    } else {
+      M.z0_used = ZF_Z0_SCALED_IDENTITY;
+      if (o.z0 == 1) M.flags |= ZF_WARN_Z0_FALLBACK;
+    }
+  }
   int rc = grow(&g_b.arena, &g_b.arena_bytes, std::max<size_t>(P.arena, 256));
   if (rc < 0) return rc;
   carve(P, (char*)g_b.arena, with64);
 
-  // metadata block: mats | full tasks | sym tasks | off_pad | off_out | S, Z0, Z pointer
-  // tables | partials | hist | g | remaining
+  // metadata block: mats | full tasks | sym tasks | S, Z0, Z pointer
+  // tables | partials | hist | g | remaining | stats | coef | feats
   size_t o_mats = 0;
   size_t o_full = align256(o_mats + sizeof(BMat) * count);
   size_t o_sym = align256(o_full + sizeof(TileTask) * P.full.size());
-  size_t o_offp = align256(o_sym + sizeof(TileTask) * P.sym.size());
-  size_t o_offo = align256(o_offp + 8 * count);
-  size_t o_ps = align256(o_offo + 8 * count);
+  size_t o_ps = align256(o_sym + sizeof(TileTask) * P.sym.size());
   size_t o_pz0 = align256(o_ps + 8 * count);
   size_t o_pz = align256(o_pz0 + 8 * count);
   size_t o_part = align256(o_pz + 8 * count);
   size_t o_hist = align256(o_part + 8 * P.partials);
   size_t o_g = align256(o_hist + 8 * (size_t)count * hcap);
   size_t o_rem = align256(o_g + 8 * count);
-  size_t total_meta = align256(o_rem + 64);
+  size_t o_stats = align256(o_rem + 64);
+  size_t o_coef = align256(o_stats + 32 * (size_t)count);
+  size_t o_feat = align256(o_coef + 32 * (size_t)count);
+  size_t total_meta = align256(o_feat + 32 * (size_t)count);
   rc = grow(&g_b.meta, &g_b.meta_bytes, total_meta);
   if (rc < 0) return rc;
   char* mb = (char*)g_b.meta;
@@ -640,26 +777,40 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   BHIP_TRY(hipMemcpyAsync(mb + o_mats, P.mats.data(), sizeof(BMat) * count, hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_full, P.full.data(), sizeof(TileTask) * P.full.size(), hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_sym, P.sym.data(), sizeof(TileTask) * P.sym.size(), hipMemcpyHostToDevice, st));
-  BHIP_TRY(hipMemcpyAsync(mb + o_offp, P.off_pad.data(), 8 * count, hipMemcpyHostToDevice, st));
-  BHIP_TRY(hipMemcpyAsync(mb + o_offo, P.off_out.data(), 8 * count, hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_ps, ps.data(), 8 * count, hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_pz0, pz0.data(), 8 * count, hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_pz, pz.data(), 8 * count, hipMemcpyHostToDevice, st));
 
   BMat* d_mats = (BMat*)(mb + o_mats);
-  const long long* d_offp = (const long long*)(mb + o_offp);
-  const long long* d_offo = (const long long*)(mb + o_offo);
   const double* const* d_S = (const double* const*)(mb + o_ps);
   const double* const* d_Z0 = (const double* const*)(mb + o_pz0);
   double* const* d_Z = (double* const*)(mb + o_pz);
   double* d_g = (double*)(mb + o_g);
+  double* d_stats = (double*)(mb + o_stats);
+  double* d_coef = (double*)(mb + o_coef);
+  float* d_feat = (float*)(mb + o_feat);
 
   // setup: operands of S and Z0
-  hipLaunchKernelGGL(b_split_kernel, dim3(grid_for_total(P.total_pad)), dim3(256), 0, st, d_mats,
-                     count, d_S, d_offp, P.total_pad, with64 ? 1 : 0);
-  hipLaunchKernelGGL(b_gersh_kernel, dim3(count), dim3(256), 0, st, d_mats, d_S, d_g);
-  hipLaunchKernelGGL(b_init_kernel, dim3(grid_for_total(P.total_pad)), dim3(256), 0, st, d_mats,
-                     count, d_Z0, d_g, d_offp, P.total_pad);
+  const dim3 eg(P.max_etiles, count);
+  hipLaunchKernelGGL(b_split_kernel, eg, dim3(256), 0, st, d_mats, d_S, with64 ? 1 : 0);
+  int cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+    cus = prop.multiProcessorCount;
+  if (n_learn > 0)
+    hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(2 * cus, (int)P.sym.size())), dim3(256), 0,
+                       st, (const TileTask*)(mb + o_sym), (int)P.sym.size(), d_mats, (int)OP_S2, 0.0,
+                       0.0, (double*)nullptr);
+  hipLaunchKernelGGL(b_stats_kernel, dim3(count), dim3(256), 0, st, d_mats, d_S, d_g, d_stats,
+                     d_feat);
+  BHIP_TRY(hipGetLastError());
+  if (n_learn > 0) {
+    rc = guess_infer_batch(d_feat, count, d_coef, st);
+    if (rc < 0) return rc;
+    hipLaunchKernelGGL(b_accept_kernel, dim3((count + 255) / 256), dim3(256), 0, st, d_mats, count,
+                       d_stats, d_coef);
+  }
+  hipLaunchKernelGGL(b_init_kernel, eg, dim3(256), 0, st, d_mats, d_Z0, d_S, d_g, d_coef);
   BHIP_TRY(hipGetLastError());
 
   Launch L;
@@ -668,15 +819,10 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   L.sym = (TileTask*)(mb + o_sym);
   L.nfull = (int)P.full.size();
   L.nsym = (int)P.sym.size();
-  L.off_pad = (long long*)d_offp;
-  L.total_pad = P.total_pad;
+  L.etiles = P.max_etiles;
   L.partials = (double*)(mb + o_part);
   L.remaining = (int*)(mb + o_rem);
   L.count = count;
-  int cus = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-    cus = prop.multiProcessorCount;
   L.grid = 2 * cus;
   L.order = o.order;
   L.rule = o.stop;
@@ -725,8 +871,7 @@ static int batched_impl(int count, const double* const* S, const double* const* 
     if (sweeps >= max_macro)
       return set_error(ZF_ERR_HIP, "batched refinement did not finish in %d macro-sweeps", sweeps);
   }
-  hipLaunchKernelGGL(b_output_kernel, dim3(grid_for_total(P.total_out)), dim3(256), 0, st, d_mats,
-                     count, d_Z, d_offo, P.total_out, with64 ? 1 : 0);
+  hipLaunchKernelGGL(b_output_kernel, eg, dim3(256), 0, st, d_mats, d_Z, with64 ? 1 : 0);
   BHIP_TRY(hipGetLastError());
   std::vector<BMat> out(count);
   BHIP_TRY(hipMemcpyAsync(out.data(), d_mats, sizeof(BMat) * count, hipMemcpyDeviceToHost, st));
@@ -753,6 +898,7 @@ static int batched_impl(int count, const double* const* S, const double* const* 
       res[m].final_err = fe;
       res[m].final_rms = fe / sqrt((double)M.n);
       res[m].status = status;
+      res[m].z0_used = M.z0_used;
     }
     if (status < 0 && first_err == 0) {
       first_err = status;

@@ -26,18 +26,20 @@
 #include "gemm_tiles.inc"
 
 namespace zf {
-template <int BM, int BN, int BK, int WM, int WN>
+// SYM is a template parameter so that the two modes are distinct kernels (and show
+// up separately in a kernel trace).
+template <int BM, int BN, int BK, int WM, int WN, bool SYM>
 __global__ void __launch_bounds__(WM* WN * 64)
     gemm_x3_kernel(const u16* __restrict__ Ahi, const u16* __restrict__ Alo, int lda,
                    const u16* __restrict__ Bhi, const u16* __restrict__ Blo, int ldb, int K,
-                   int tiles_n, int sym, EpiParams ep) {
+                   int tiles_n, int gm, EpiParams ep) {
   using C = X3Cfg<BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) u16 lds[2 * C::STAGE_ELEMS];
   __shared__ double red[C::NT / 64];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   int ti, tj;
-  tile_coords(bid, tiles_n, sym, ti, tj);
-  const int mode = sym ? (ti == tj ? 2 : 1) : 0;
+  tile_coords(bid, tiles_n, SYM, ti, tj, gm);
+  const int mode = SYM ? (ti == tj ? 2 : 1) : 0;
   x3_tile<BM, BN, BK, WM, WN>(Ahi, Alo, lda, Bhi, Blo, ldb, K, ti * BM, tj * BN, mode, ep,
                               blockIdx.x, lds, red);
 }
@@ -45,17 +47,17 @@ __global__ void __launch_bounds__(WM* WN * 64)
 // ---------------------------------------------------------------------------
 // FP64 kernel
 // ---------------------------------------------------------------------------
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, bool SYM>
 __global__ void __launch_bounds__(WM* WN * 64, 2)
     gemm_f64_kernel(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
-                    int K, int tiles_n, int sym, EpiParams ep) {
+                    int K, int tiles_n, int gm, EpiParams ep) {
   using C = F64Cfg<BM, BN, BK, WM, WN>;
   __shared__ double lds[2 * C::STAGE];
   __shared__ double red[C::NT / 64];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   int ti, tj;
-  tile_coords(bid, tiles_n, sym, ti, tj);
-  const int mode = sym ? (ti == tj ? 2 : 1) : 0;
+  tile_coords(bid, tiles_n, SYM, ti, tj, gm);
+  const int mode = SYM ? (ti == tj ? 2 : 1) : 0;
   f64_tile<BM, BN, BK, WM, WN>(A, lda, B, ldb, K, ti * BM, tj * BN, mode, ep, blockIdx.x, lds, red);
 }
 
@@ -89,13 +91,53 @@ int x3_tile_edge(int M, int N, bool sym) {
 
 int x3_blocks(int M, int N, bool sym) { return grid_blocks(M, N, x3_tile_edge(M, N, sym), sym); }
 
+// FP64 tile edge: 64.  The 64-wide tile runs four blocks per CU at the same
+// per-flop rate as the 128-wide one (both ~82% of FP64 peak on full N = 4096
+// grids) and quantizes far better on triangular grids (N = 4096: 2080 blocks
+// instead of 528 on 512 two-per-CU slots).  ZF_F64_TILE / ZF_F64_SYM_TILE = 128
+// select the larger tile (tuning).
 int f64_tile_edge(int M, int N, bool sym) {
-  return grid_blocks(M, N, 128, sym) >= 128 ? 128 : 64;
+  const char* env = getenv(sym ? "ZF_F64_SYM_TILE" : "ZF_F64_TILE");
+  if (env && atoi(env) == 128 && M % 128 == 0 && N % 128 == 0) return 128;
+  return 64;
+}
+
+// Row-group height of the full-grid tile order: 4 (a run of 32 tiles on one XCD then
+// covers 4 x 8 tiles, 12 operand panels instead of 18); ZF_TILE_GROUP overrides.
+static int tile_group(int M, int t) {
+  const char* env = getenv("ZF_TILE_GROUP");
+  const int gm = env ? atoi(env) : 4;
+  return (gm > 1 && (M / t) % gm == 0) ? gm : 1;
 }
 
 int f64_blocks(int M, int N, bool sym) { return grid_blocks(M, N, f64_tile_edge(M, N, sym), sym); }
 
 int max_blocks(int M, int N) { return grid_blocks(M, N, 64, false); }
+
+template <int BM, int BN, int WM, int WN>
+static void x3_launch(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
+                      int ldb, int M, int N, int K, bool sym, int blocks, const EpiParams& ep,
+                      hipStream_t st) {
+  if (sym)
+    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, true>), dim3(blocks), dim3(WM * WN * 64),
+                       0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, 1, ep);
+  else
+    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, false>), dim3(blocks),
+                       dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN,
+                       tile_group(M, BM), ep);
+}
+
+template <int BM, int BN, int WM, int WN>
+static void f64_launch(const double* A, int lda, const double* B, int ldb, int M, int N, int K,
+                       bool sym, int blocks, const EpiParams& ep, hipStream_t st) {
+  if (sym)
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, 16, WM, WN, true>), dim3(blocks),
+                       dim3(WM * WN * 64), 0, st, A, lda, B, ldb, K, N / BN, 1, ep);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, 16, WM, WN, false>), dim3(blocks),
+                       dim3(WM * WN * 64), 0, st, A, lda, B, ldb, K, N / BN, tile_group(M, BM),
+                       ep);
+}
 
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
@@ -103,19 +145,12 @@ hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bh
   if (!dims_ok(M, N, K, sym)) return hipErrorInvalidValue;
   const int tile = x3_tile_edge(M, N, sym);
   const int blocks = x3_blocks(M, N, sym);
-  if (tile == 256) {
-    constexpr int BM = 256, BN = 256, BK = 32, WM = 2, WN = 4;
-    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
-                       st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym ? 1 : 0, ep);
-  } else if (tile == 128) {
-    constexpr int BM = 128, BN = 128, BK = 32, WM = 2, WN = 2;
-    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
-                       st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym ? 1 : 0, ep);
-  } else {
-    constexpr int BM = 64, BN = 64, BK = 32, WM = 2, WN = 2;
-    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
-                       st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym ? 1 : 0, ep);
-  }
+  if (tile == 256)
+    x3_launch<256, 256, 2, 4>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+  else if (tile == 128)
+    x3_launch<128, 128, 2, 2>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+  else
+    x3_launch<64, 64, 2, 2>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
   return hipGetLastError();
 }
 
@@ -123,15 +158,10 @@ hipError_t launch_gemm_f64(const double* A, int lda, const double* B, int ldb, i
                            bool sym, const EpiParams& ep, hipStream_t st) {
   if (!dims_ok(M, N, K, sym)) return hipErrorInvalidValue;
   const int blocks = f64_blocks(M, N, sym);
-  if (f64_tile_edge(M, N, sym) == 128) {
-    constexpr int BM = 128, BN = 128, BK = 16, WM = 2, WN = 2;
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
-                       st, A, lda, B, ldb, K, N / BN, sym ? 1 : 0, ep);
-  } else {
-    constexpr int BM = 64, BN = 64, BK = 16, WM = 2, WN = 2;
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN>), dim3(blocks), dim3(WM * WN * 64), 0,
-                       st, A, lda, B, ldb, K, N / BN, sym ? 1 : 0, ep);
-  }
+  if (f64_tile_edge(M, N, sym) == 128)
+    f64_launch<128, 128, 2, 2>(A, lda, B, ldb, M, N, K, sym, blocks, ep, st);
+  else
+    f64_launch<64, 64, 2, 2>(A, lda, B, ldb, M, N, K, sym, blocks, ep, st);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 // <St^k, Z>, k = 1..3, which zf_guess_label evaluates with FP64 GEMMs.
 // Training (forward, MSE, backward, Adam) and inference are the kernels below.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <vector>
@@ -150,6 +151,7 @@ struct Net {
   float* m = nullptr;       // Adam moments
   float* v = nullptr;
   float* norm = nullptr;    // mu_x[8], sd_x[8], mu_y[3], sd_y[3]
+  float h_norm[32] = {0};   // host copy of norm (for zf_mlp_save)
   double* coef = nullptr;   // prediction output (3 doubles)
   int step = 0;
   bool has_params = false, has_norm = false;
@@ -328,15 +330,7 @@ int guess_features(const double* S, int n, const double* S2, const float* S2f, i
 __global__ void features_finish_kernel(const double* __restrict__ gs, const double* __restrict__ dots,
                                        int n, float* feats) {
   if (threadIdx.x != 0) return;
-  const double g = gs[0], glo = gs[1], rmean = gs[2], trS = gs[3];
-  feats[0] = (float)log((double)n);
-  feats[1] = (float)(trS / g / n);
-  feats[2] = (float)(dots[0] / (g * g) / n);        // ||S||_F^2
-  feats[3] = (float)(dots[1] / (g * g * g) / n);    // <S, S^2>
-  feats[4] = (float)(dots[2] / (g * g * g * g) / n);  // ||S^2||_F^2
-  feats[5] = (float)(fmax(glo, 0.0) / g);
-  feats[6] = (float)(glo / g);
-  feats[7] = (float)(rmean / g);
+  finish_features(gs[0], gs[1], gs[2], gs[3], dots[0], dots[1], dots[2], n, feats);
 }
 
 // ||S||^2, <S, S^2>, ||S^2||^2 over the valid block (S2 in FP64 or FP32)
@@ -381,10 +375,13 @@ int guess_features(const double* S, int n, const double* S2, const float* S2f, i
 
 // network inference on one feature vector (device) -> standardized-back coefficients
 // (device, 3 doubles); returns ZF_ERR_ARG when no parameters are loaded.
+// one block of NH threads per feature vector; coefficients at coef + 4 * block
 __global__ void mlp_infer_kernel(const float* __restrict__ P, const float* __restrict__ norm,
-                                 const float* __restrict__ feats, double* coef) {
+                                 const float* __restrict__ feats_all, double* coef_all) {
   __shared__ float x[NF], h1[NH], h2[NH];
   const int j = threadIdx.x;
+  const float* feats = feats_all + (size_t)NF * blockIdx.x;
+  double* coef = coef_all + (size_t)4 * blockIdx.x;
   if (j < NF) x[j] = (feats[j] - norm[j]) / norm[NF + j];
   __syncthreads();
   float s = P[OFF_B1 + j];
@@ -411,25 +408,16 @@ int guess_infer(const float* feats, double* coef, hipStream_t st) {
   return 0;
 }
 
-// Acceptance on the Gershgorin interval (see the file header): rescale so that
-// max_x x p(x)^2 <= 1.9, reject if p <= 0 somewhere on (x_lo, 1].
-bool guess_accept(double c[3], double x_lo) {
-  const int K = 1024;
-  if (x_lo < 0.0) x_lo = 0.0;
-  double mx = 0.0;
-  for (int k = 0; k <= K; ++k) {
-    const double x = x_lo + (1.0 - x_lo) * k / K;
-    const double p = c[0] + c[1] * x + c[2] * x * x;
-    if (p <= 0.0 && (x > 0.0)) return false;
-    mx = fmax(mx, x * p * p);
-  }
-  if (!(mx > 0.0)) return false;
-  if (mx > 1.9) {
-    const double s = sqrt(1.9 / mx);
-    for (int k = 0; k < 3; ++k) c[k] *= s;
-  }
-  return true;
+int guess_infer_batch(const float* feats, int count, double* coef, hipStream_t st) {
+  if (!net_ready()) return set_error(ZF_ERR_ARG, "no network parameters / normalization loaded");
+  if (count <= 0) return 0;
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3(count), dim3(NH), 0, st, g_net.params, g_net.norm, feats,
+                     coef);
+  GHIP_TRY(hipGetLastError());
+  return 0;
 }
+
+bool guess_accept(double c[3], double x_lo) { return accept_poly(c, x_lo); }
 
 hipError_t launch_guess_write(const double* S, int n, const double* S2, const float* S2f, int np,
                               const double* cg, float* z32, double* z64r, double* z64c, u16* zr_hi,
@@ -503,8 +491,54 @@ int zf_mlp_set_norm(const float* mu_x, const float* sd_x, const float* mu_y, con
   memcpy(h + 2 * NF, mu_y, NO * 4);
   memcpy(h + 2 * NF + NO, sd_y, NO * 4);
   GHIP_TRY(hipMemcpy(g_net.norm, h, 32 * 4, hipMemcpyHostToDevice));
+  memcpy(g_net.h_norm, h, sizeof h);
   g_net.has_norm = true;
   return 0;
+}
+
+// File layout (little-endian): 8-byte magic "ZFMLP\0\0\1", int32 {8, 64, 3, 4931},
+// float32 mu_x[8], sd_x[8], mu_y[3], sd_y[3], float32 parameters[4931].
+static const char kMagic[8] = {'Z', 'F', 'M', 'L', 'P', 0, 0, 1};
+
+int zf_mlp_save(const char* path) {
+  if (!path) return set_error(ZF_ERR_ARG, "NULL path");
+  if (!net_ready()) return set_error(ZF_ERR_ARG, "no network parameters / normalization loaded");
+  std::vector<float> p(NPARAM);
+  GHIP_TRY(hipMemcpy(p.data(), g_net.params, NPARAM * 4, hipMemcpyDeviceToHost));
+  FILE* f = fopen(path, "wb");
+  if (!f) return set_error(ZF_ERR_ARG, "cannot open %s for writing", path);
+  const int32_t dims[4] = {NF, NH, NO, NPARAM};
+  bool ok = fwrite(kMagic, 1, 8, f) == 8 && fwrite(dims, 4, 4, f) == 4 &&
+            fwrite(g_net.h_norm, 4, 2 * NF + 2 * NO, f) == (size_t)(2 * NF + 2 * NO) &&
+            fwrite(p.data(), 4, NPARAM, f) == (size_t)NPARAM;
+  ok = (fclose(f) == 0) && ok;
+  if (!ok) return set_error(ZF_ERR_ARG, "short write to %s", path);
+  return 0;
+}
+
+int zf_mlp_load(const char* path) {
+  if (!path) return set_error(ZF_ERR_ARG, "NULL path");
+  FILE* f = fopen(path, "rb");
+  if (!f) return set_error(ZF_ERR_ARG, "cannot open %s", path);
+  char magic[8];
+  int32_t dims[4];
+  float nrm[2 * NF + 2 * NO];
+  std::vector<float> p(NPARAM);
+  const bool ok = fread(magic, 1, 8, f) == 8 && fread(dims, 4, 4, f) == 4 &&
+                  fread(nrm, 4, 2 * NF + 2 * NO, f) == (size_t)(2 * NF + 2 * NO) &&
+                  fread(p.data(), 4, NPARAM, f) == (size_t)NPARAM;
+  const bool trailing = ok && fgetc(f) != EOF;
+  fclose(f);
+  if (!ok || trailing || memcmp(magic, kMagic, 8) != 0)
+    return set_error(ZF_ERR_ARG, "%s is not a network file of this library", path);
+  if (dims[0] != NF || dims[1] != NH || dims[2] != NO || dims[3] != NPARAM)
+    return set_error(ZF_ERR_ARG, "%s: network shape %d-%d-%d (%d parameters) differs from 8-64-3",
+                     path, dims[0], dims[1], dims[2], dims[3]);
+  for (int k = 0; k < NPARAM; ++k)
+    if (!isfinite(p[k])) return set_error(ZF_ERR_ARG, "%s: parameter %d is not finite", path, k);
+  int rc = zf_mlp_set_norm(nrm, nrm + NF, nrm + 2 * NF, nrm + 2 * NF + NO);
+  if (rc < 0) return rc;
+  return zf_mlp_set_params(p.data(), NPARAM);
 }
 
 static int train_common(const float* feats, const float* labels, int batch, hipStream_t st,

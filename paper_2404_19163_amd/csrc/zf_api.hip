@@ -531,19 +531,19 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   // setup: operands of S, then Z0
   HIP_TRY(launch_split_pad(S, n, n, np, mixed ? w->s_hi : nullptr, mixed ? w->s_lo : nullptr,
                            (use_h || learned) ? w->s64 : nullptr, nullptr, false, 1, st));
-  int z0_used = Z0 ? 0 : 1;
+  int z0_used = Z0 ? ZF_Z0_GIVEN : ZF_Z0_SCALED_IDENTITY;
   int guess_flags = 0;
   if (learned) {
     int lr = learned_guess(c, S, mixed, use_h, st);
     if (lr < 0) return lr;
-    if (lr == 1) z0_used = 2;
+    if (lr == 1) z0_used = ZF_Z0_LEARNED;
     else guess_flags |= ZF_WARN_Z0_FALLBACK;
   }
   if (Z0) {
     HIP_TRY(launch_init_given(Z0, n, np, mixed ? w->z32[0] : nullptr, use_h ? w->z64r[0] : nullptr,
                               use_h ? w->z64c[0] : nullptr, w->zr_hi[0], w->zr_lo[0],
                               mixed ? w->zc_hi[0] : nullptr, mixed ? w->zc_lo[0] : nullptr, st));
-  } else if (z0_used == 2) {
+  } else if (z0_used == ZF_Z0_LEARNED) {
     // written by learned_guess
   } else {
     HIP_TRY(launch_row_abs_max(S, n, n, w->rowsum, w->g_dev, st));

@@ -44,6 +44,47 @@ __device__ __forceinline__ void split_f16(float x, u16& hi, u16& lo) {
 }
 
 // ---------------------------------------------------------------------------
+// Learned guess helpers shared by the single-matrix and batched paths.
+// ---------------------------------------------------------------------------
+// The 8 network features from the Gershgorin statistics (g = max r_i, g_lo, mean r_i),
+// tr S and the Frobenius products ||S||^2, <S, S^2>, ||S^2||^2 (= N times the mean
+// of the k-th power of the spectrum of S/g for k = 1..4).
+__host__ __device__ inline void finish_features(double g, double glo, double rmean, double trS,
+                                                double d0, double d1, double d2, int n,
+                                                float* f) {
+  f[0] = (float)log((double)n);
+  f[1] = (float)(trS / g / n);
+  f[2] = (float)(d0 / (g * g) / n);
+  f[3] = (float)(d1 / (g * g * g) / n);
+  f[4] = (float)(d2 / (g * g * g * g) / n);
+  f[5] = (float)(fmax(glo, 0.0) / g);
+  f[6] = (float)(glo / g);
+  f[7] = (float)(rmean / g);
+}
+
+// Acceptance of p(x) = c0 + c1 x + c2 x^2 on the Gershgorin interval [x_lo, 1]: the
+// eigenvalues of X0 = Z0^T S Z0 are x p(x)^2 (x = lambda / g), and convergence needs
+// them in (0, 2) (||X0 - I||_2 < 1, Sec. III).  Rejects if p <= 0 at a sampled x > 0,
+// else rescales c so that the sampled maximum of x p(x)^2 is at most 1.9.
+__host__ __device__ inline bool accept_poly(double c[3], double x_lo) {
+  const int K = 1024;
+  if (x_lo < 0.0) x_lo = 0.0;
+  double mx = 0.0;
+  for (int k = 0; k <= K; ++k) {
+    const double x = x_lo + (1.0 - x_lo) * k / K;
+    const double p = c[0] + c[1] * x + c[2] * x * x;
+    if (p <= 0.0 && (x > 0.0)) return false;
+    mx = fmax(mx, x * p * p);
+  }
+  if (!(mx > 0.0)) return false;
+  if (mx > 1.9) {
+    const double s = sqrt(1.9 / mx);
+    for (int k = 0; k < 3; ++k) c[k] *= s;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // GEMM epilogue: out = alpha * D + beta * acc + gamma * I  (I restricted to the
 // valid n_valid x n_valid block so that zero padding stays exactly zero).
 // Every output pointer is optional.  Normal outputs are written at
@@ -115,6 +156,8 @@ void batch_release_all();  // frees the batched path's cached state (batched.hip
 int guess_features(const double* S, int n, const double* S2, const float* S2f, int np,
                    const double* S64pad, float* feats, double* scratch, hipStream_t st);
 int guess_infer(const float* feats, double* coef, hipStream_t st);
+// count feature vectors (8 floats each) -> count x {c0, c1, c2, .} (stride 4 doubles)
+int guess_infer_batch(const float* feats, int count, double* coef, hipStream_t st);
 bool net_ready();
 bool guess_accept(double c[3], double x_lo);
 hipError_t launch_guess_write(const double* S, int n, const double* S2, const float* S2f, int np,

@@ -59,12 +59,10 @@ def train(feats: np.ndarray, labels: np.ndarray, steps: int = 500, lr: float = 3
     return [zf.mlp_train_step(F, L, lr) for _ in range(steps)], norm
 
 
-def save(path: str, norm) -> None:
-    mu_x, sd_x, mu_y, sd_y = norm
-    np.savez(path, params=zf.mlp_get_params(), mu_x=mu_x, sd_x=sd_x, mu_y=mu_y, sd_y=sd_y)
+def save(path: str) -> None:
+    """The loaded network to a file (the library's zf_mlp_save format)."""
+    zf.mlp_save(path)
 
 
 def load(path: str) -> None:
-    d = np.load(path, allow_pickle=False)
-    zf.mlp_set_norm(d["mu_x"], d["sd_x"], d["mu_y"], d["sd_y"])
-    zf.mlp_set_params(d["params"])
+    zf.mlp_load(path)

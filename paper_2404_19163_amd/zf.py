@@ -57,7 +57,7 @@ EXPORTS = ("zf_default_opts", "zf_refine", "zf_refine_ex", "zf_residual", "zf_re
            "zf_batched_set_tiles", "zf_batched_get_tiles", "zf_batched_autotune",
            "zf_batched_use_graph", "zf_batched_release", "zf_features", "zf_guess_label",
            "zf_mlp_set_params", "zf_mlp_get_params", "zf_mlp_set_norm", "zf_mlp_train_step",
-           "zf_mlp_grad", "zf_mlp_predict")
+           "zf_mlp_grad", "zf_mlp_predict", "zf_mlp_save", "zf_mlp_load")
 N_PARAMS = 4931
 
 _lib = None
@@ -128,6 +128,10 @@ def lib() -> ctypes.CDLL:
     L.zf_mlp_grad.restype = i
     L.zf_mlp_predict.argtypes = [vp, P(d), vp]
     L.zf_mlp_predict.restype = i
+    L.zf_mlp_save.argtypes = [ctypes.c_char_p]
+    L.zf_mlp_save.restype = i
+    L.zf_mlp_load.argtypes = [ctypes.c_char_p]
+    L.zf_mlp_load.restype = i
     _lib = L
     return L
 
@@ -204,9 +208,10 @@ class BatchResult:
 def refine_batched(S_list, Z0_list=None, *, order: int = 2, precision: str = "bf16x3",
                    stop: str = "ratio", max_sweeps: int = 100, refine: str = "f64_delta",
                    max_refine: int = 10, out=None, hist_cap: int = 64, stream=None,
-                   raise_on_error: bool = True) -> BatchResult:
-    """Refine many matrices together (zf_refine_batched).  Returns one Refined per
-    matrix (with .status) and the call's return code."""
+                   raise_on_error: bool = True, guess: str = "identity") -> BatchResult:
+    """Refine many matrices together (zf_refine_batched).  Matrices without a Z0 start
+    from the scaled identity, or the learned polynomial (guess="learned").  Returns one
+    Refined per matrix (with .status and .z0_used) and the call's return code."""
     count = len(S_list)
     ns = [int(S.shape[0]) for S in S_list]
     sp = (ctypes.c_void_p * count)(*[_dev(S, "S", n) for S, n in zip(S_list, ns)])
@@ -219,7 +224,8 @@ def refine_batched(S_list, Z0_list=None, *, order: int = 2, precision: str = "bf
         out = [torch.empty_like(S) for S in S_list]
     zp = (ctypes.c_void_p * count)(*[_dev(Z, "out", n) for Z, n in zip(out, ns)])
     narr = (ctypes.c_int * count)(*ns)
-    o = Opts(order, _PREC[precision], _STOP[stop], max_sweeps, _REFINE[refine], max_refine, 0)
+    o = Opts(order, _PREC[precision], _STOP[stop], max_sweeps, _REFINE[refine], max_refine,
+             1 if guess == "learned" else 0)
     res = (Result * count)()
     hist = (ctypes.c_double * max(count * hist_cap, 1))()
     rc = lib().zf_refine_batched(count, sp, z0p, narr, ctypes.byref(o), zp, res, hist, hist_cap,
@@ -233,6 +239,7 @@ def refine_batched(S_list, Z0_list=None, *, order: int = 2, precision: str = "bf
         outl.append(Refined(out[m], r.iters, h, r.low_evals, r.high_evals, r.flags, r.final_err,
                             r.final_rms))
         outl[-1].status = r.status
+        outl[-1].z0_used = r.z0_used
     return BatchResult(outl, rc)
 
 
@@ -429,3 +436,13 @@ def mlp_predict(feat: torch.Tensor, stream=None):
     c = (ctypes.c_double * 3)()
     _check(lib().zf_mlp_predict(feat.data_ptr(), c, _stream(stream)))
     return [c[0], c[1], c[2]]
+
+
+def mlp_save(path) -> None:
+    """Write the loaded network (normalization + parameters) to path (zf_mlp_save)."""
+    _check(lib().zf_mlp_save(os.fsencode(path)))
+
+
+def mlp_load(path) -> None:
+    """Load a network written by mlp_save (zf_mlp_load)."""
+    _check(lib().zf_mlp_load(os.fsencode(path)))

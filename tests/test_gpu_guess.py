@@ -106,28 +106,38 @@ def test_fallback_without_network(zf):
     del lib
 
 
-def test_learned_guess_saves_sweeps(zf):
-    """Train on matrices the method refines, then compare update counts on held-out
-    matrices of the same family."""
+def _family(count, seed):
+    """Gaussian-kernel overlaps of order 64..256, sigma 0.9..1.3 (one training family)."""
+    out = []
+    r = np.random.default_rng(seed)
+    for _ in range(count):
+        n = int(r.integers(64, 257))
+        sigma = float(r.uniform(0.9, 1.3))
+        out.append(inputs.overlap_gaussian(n, sigma, int(r.integers(1 << 30))))
+    return out
+
+
+@pytest.fixture(scope="module")
+def trained(zf):
+    """A network trained on 48 matrices of the family (labels from the method's own Z)."""
     from paper_2404_19163_amd import guess
-    rng = np.random.default_rng(11)
+    X, Y = guess.training_pairs(_family(48, 1))
+    losses, norm = guess.train(X, Y, steps=400, lr=3e-3, seed=0)
+    return zf.mlp_get_params(), norm, losses
 
-    def family(count, seed):
-        out = []
-        r = np.random.default_rng(seed)
-        for _ in range(count):
-            n = int(r.integers(64, 257))
-            sigma = float(r.uniform(0.9, 1.3))
-            out.append(inputs.overlap_gaussian(n, sigma, int(r.integers(1 << 30))))
-        return out
 
-    train_set = family(48, 1)
-    X, Y = guess.training_pairs(train_set)
-    losses, _ = guess.train(X, Y, steps=400, lr=3e-3, seed=0)
-    assert losses[-1] < losses[0]
-    held = family(10, 2)
+def _install(zf, trained):
+    params, norm, _ = trained
+    zf.mlp_set_norm(*norm)
+    zf.mlp_set_params(params)
+
+
+def test_learned_guess_saves_sweeps(zf, trained):
+    """Compare update counts on held-out matrices of the training family."""
+    _install(zf, trained)
+    assert trained[2][-1] < trained[2][0]
     gain = []
-    for S in held:
+    for S in _family(10, 2):
         Sd = _cuda(S)
         r_id = zf.refine(Sd, None, precision="bf16x3")
         r_lg = zf.refine(Sd, None, precision="bf16x3", guess="learned")
@@ -136,4 +146,77 @@ def test_learned_guess_saves_sweeps(zf):
         gain.append(r_id.low_evals - r_lg.low_evals)
     print("low-precision sweeps saved per matrix:", gain)
     assert np.mean(gain) > 0.5
-    del rng
+
+
+def test_batched_learned_guess(zf, trained):
+    """Batched learned guesses: the device acceptance takes the oracle's decision on
+    the network's coefficients, every matrix converges to S^(-1/2) (a polynomial guess
+    commutes with S), sweep counts follow the single-matrix learned path, and the
+    batch saves sweeps over the scaled identity."""
+    _install(zf, trained)
+    held = _family(12, 3)
+    Sd = [_cuda(S) for S in held]
+    out = zf.refine_batched(Sd, guess="learned")
+    ident = zf.refine_batched(Sd)
+    assert out.rc >= 0
+    gains = []
+    for S, Sdev, rb, ri in zip(held, Sd, out.results, ident.results):
+        c = np.array(zf.mlp_predict(zf.features(Sdev)))
+        g, glo, _ = G.gershgorin(S)
+        want = zf.Z0_LEARNED if G.accept(c, max(glo, 0.0) / g) is not None else zf.Z0_SCALED_IDENTITY
+        assert rb.z0_used == want
+        assert rb.status == 0
+        Z = rb.Z.cpu().numpy()
+        assert O.residual_rms(S, Z) <= 1e-6
+        L = O.lowdin(S)
+        assert np.linalg.norm(Z - L) / np.linalg.norm(L) <= 1e-4
+        rs = zf.refine(Sdev, None, precision="bf16x3", guess="learned")
+        assert rs.z0_used == rb.z0_used
+        assert abs(rs.low_evals - rb.low_evals) <= 1
+        gains.append(ri.low_evals - rb.low_evals)
+    print("batched low-precision sweeps saved per matrix:", gains)
+    assert np.mean(gains) > 0.5
+
+
+def test_batched_learned_fallback_and_given(zf):
+    """A network whose p is negative everywhere is rejected per matrix (scaled identity,
+    flagged); a given Z0 in the same batch is used as given."""
+    from paper_2404_19163_amd import guess
+    zf.mlp_set_norm(np.zeros(8), np.ones(8), np.array([-5.0, 0, 0]), np.ones(3))
+    zf.mlp_set_params(np.zeros(guess.N_PARAMS, dtype=np.float32))
+    mats = [inputs.overlap_gaussian(n, 1.2, 20 + n) for n in (96, 150, 200)]
+    Z0 = [None, O.lowdin(mats[1]) + 1e-3 * inputs.uniform_noise(150, 4), None]
+    out = zf.refine_batched([_cuda(S) for S in mats], [None if z is None else _cuda(z) for z in Z0],
+                            guess="learned")
+    assert out.rc >= 0 and out.rc & zf.WARN_Z0_FALLBACK
+    used = [r.z0_used for r in out.results]
+    assert used == [zf.Z0_SCALED_IDENTITY, zf.Z0_GIVEN, zf.Z0_SCALED_IDENTITY]
+    assert [bool(r.flags & zf.WARN_Z0_FALLBACK) for r in out.results] == [True, False, True]
+    for S, r in zip(mats, out.results):
+        assert O.residual_rms(S, r.Z.cpu().numpy()) <= 1e-6
+
+
+def test_network_file_round_trip(zf, trained, tmp_path):
+    """zf_mlp_save / zf_mlp_load restore the same predictions; malformed files are
+    refused without touching the loaded network."""
+    _install(zf, trained)
+    f = zf.features(_cuda(inputs.overlap_gaussian(120, 1.1, 9)))
+    c0 = zf.mlp_predict(f)
+    path = tmp_path / "net.zfmlp"
+    zf.mlp_save(str(path))
+    assert path.stat().st_size == 8 + 16 + 4 * 22 + 4 * zf.N_PARAMS
+    from paper_2404_19163_amd import guess
+    zf.mlp_set_params(guess.init_params(7))
+    assert zf.mlp_predict(f) != c0
+    zf.mlp_load(str(path))
+    assert zf.mlp_predict(f) == c0
+    np.testing.assert_array_equal(zf.mlp_get_params(), trained[0])
+    raw = path.read_bytes()
+    bad = tmp_path / "bad.zfmlp"
+    for blob in (raw[:-4], raw + b"x", b"XXXXXXXX" + raw[8:]):
+        bad.write_bytes(blob)
+        with pytest.raises(zf.ZFError):
+            zf.mlp_load(str(bad))
+    assert zf.mlp_predict(f) == c0
+    with pytest.raises(zf.ZFError):
+        zf.mlp_load(str(tmp_path / "missing"))

@@ -69,12 +69,15 @@ def test_split_empty(zf):
     assert hi.numel() == 0
 
 
-SHAPES = [(128, 128, 128), (200, 200, 300), (96, 260, 70), (1, 1, 1), (384, 256, 513), (640, 640, 384)]
+SHAPES = [(128, 128, 128), (200, 200, 300), (96, 260, 70), (1, 1, 1), (384, 256, 513), (640, 640, 384),
+          (1024, 512, 256)]   # the last: 16 x 8 tile grid walked in groups of 4 rows
 
 
+@pytest.mark.parametrize("tile", ["64", "128"])
 @pytest.mark.parametrize("m,nn,k", SHAPES + [(1536, 1536, 256)])
-def test_gemm_f64(zf, m, nn, k):
-    """Small outputs take 64-wide tiles, 1536^2 and up 128-wide ones."""
+def test_gemm_f64(zf, m, nn, k, tile, monkeypatch):
+    """Both FP64 tile edges (64 is the default; 128 when ZF_F64_TILE asks and divides)."""
+    monkeypatch.setenv("ZF_F64_TILE", tile)
     rng = np.random.default_rng(m * 7 + nn + k)
     A = rng.standard_normal((m, k))
     B = rng.standard_normal((nn, k))
@@ -103,7 +106,7 @@ def test_gemm_bf16x3(zf, m, nn, k, tile, monkeypatch):
     assert np.all(np.abs(C - exact) <= (3 * u * u + 3 * k * U32) * (np.abs(A) @ np.abs(B).T) * 1.01)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "bf16x3-t128", "bf16x3-t64"])
+@pytest.mark.parametrize("prec", ["fp64", "fp64-t128", "bf16x3", "bf16x3-t128", "bf16x3-t64"])
 @pytest.mark.parametrize("n,k", [(128, 128), (300, 200), (640, 512), (129, 64), (1000, 256),
                                  (2048, 128)])
 def test_gemm_symmetric_delta_epilogue(zf, prec, n, k, monkeypatch):
@@ -117,7 +120,7 @@ def test_gemm_symmetric_delta_epilogue(zf, prec, n, k, monkeypatch):
     B = A @ M                     # A B^T = A M A^T is symmetric
     if "-t" in prec:
         prec, tile = prec.split("-t")
-        monkeypatch.setenv("ZF_X3_SYM_TILE", tile)
+        monkeypatch.setenv("ZF_X3_SYM_TILE" if prec == "bf16x3" else "ZF_F64_SYM_TILE", tile)
     C, nsq = zf.t_gemm(prec, _cuda(A), _cuda(B), sym=True, beta=-1.0, gamma=1.0)
     C = C.cpu().numpy()
     assert np.array_equal(C, C.T)
