@@ -13,9 +13,10 @@ struct X3Cfg {
   static constexpr int WTM = BM / WM, WTN = BN / WN;
   static constexpr int FM = WTM / 32, FN = WTN / 32;
   static constexpr int STAGE = (BM + BN) * 2 * BK;  // 16-bit elements per pipeline stage
-  static constexpr int SP = BN + 1;                  // epilogue strip pitch (floats)
-  // a stage buffer also holds one 32-row epilogue strip
-  static constexpr int STAGE_ELEMS = (STAGE > 32 * SP * 2) ? STAGE : 32 * SP * 2;
+  static constexpr int SP = BN + 1;                  // epilogue strip pitch (elements)
+  // the two stage buffers also hold the epilogue's 32-row strips: FP32 accumulators
+  // then FP64 values, 32 SP (4 + 8) bytes = 192 SP 16-bit elements
+  static constexpr int STAGE_ELEMS = (2 * STAGE > 192 * SP) ? STAGE : 96 * SP;
   static_assert(BK == 32, "the LDS swizzle assumes 64-byte tile rows");
   static_assert(BM % (WM * 32) == 0 && BN % (WN * 32) == 0, "wave tile");
 };
