@@ -38,6 +38,8 @@ WORKLOADS = {
                            "addition, d_min 0.8 A), S_ij=exp(-r^2/2), sigma 1.0 A"),
     "gauss256": dict(n=256, sigma=1.2,
                      desc="Gaussian-kernel overlap, N=256, sigma 1.2 A"),
+    "gauss3000": dict(n=3000, sigma=1.0,
+                      desc="Gaussian-kernel overlap, N=3000, sigma 1.0 A (one frame of md3000)"),
     "cluster5049": dict(n=5049, sigma=None,
                         desc="561-atom fcc cuboctahedron, 1s+3p+5d Gaussians, alpha 0.08 bohr^-2, "
                              "N=5049"),

@@ -91,6 +91,7 @@ int x3_tile_edge(int M, int N, bool sym) {
 
 int x3_blocks(int M, int N, bool sym) { return grid_blocks(M, N, x3_tile_edge(M, N, sym), sym); }
 
+
 // FP64 tile edge: 64.  The 64-wide tile runs four blocks per CU at the same
 // per-flop rate as the 128-wide one (both ~82% of FP64 peak on full N = 4096
 // grids) and quantizes far better on triangular grids (N = 4096: 2080 blocks
