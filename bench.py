@@ -30,6 +30,31 @@ if ROOT not in sys.path:
 METRIC = ("refined-Z TFLOP/s + time-to-‖ZᵀSZ−I‖≤1e-6, mixed vs FP64 path, "
           "1 MI355X")
 PEAK_TFLOPS = {"bf16": 2500.0, "fp64": 78.6}
+# Sources of the GEMM kernels; an HBM-traffic record in profiles/ is used only while
+# they hash to the value it was measured with.
+GEMM_SOURCES = ["paper_2404_19163_amd/csrc/gemm.hip", "paper_2404_19163_amd/csrc/gemm_tiles.inc",
+                "paper_2404_19163_amd/csrc/zf_tiles.h", "paper_2404_19163_amd/csrc/zf_internal.h"]
+TRAFFIC_PROFILE = "profiles/gemm_gauss4096.md"
+
+
+def measured_traffic(kernel: str, n: int):
+    """(HBM bytes per launch, algorithmic bytes per launch) of `kernel` at order n from
+    the rocprofv3 FETCH_SIZE / WRITE_SIZE record in profiles/, or (None, None) when
+    there is none or the kernel sources changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, TRAFFIC_PROFILE)).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        h = hashlib.sha256()
+        for f in GEMM_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+    except (OSError, AttributeError, ValueError):
+        return None, None
+    if rec.get("kernel") != kernel or rec.get("n") != n or rec.get("sources_sha256") != h.hexdigest():
+        return None, None
+    return rec["traffic_bytes_per_dispatch"], rec.get("alg_bytes_per_dispatch")
 KCLASS_DTYPE = {"gemm_x3": "bf16", "gemm_x3_sym": "bf16", "gemm_f64": "fp64", "gemm_f64_sym": "fp64"}
 
 WORKLOADS = {
@@ -190,6 +215,7 @@ def main() -> int:
                "sample": f"{args.workload}: 2 FP64 residual evaluations + 1 update of the oracle "
                          f"recursion ({cf:.3e} alg. flops) in {cpu_s:.2f} s"}
 
+    traffic, alg_bytes = measured_traffic(dom, n)
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -216,7 +242,10 @@ def main() -> int:
         "checks": checks,
         "kernels": kernels,
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(ach, 2), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None},
+                     "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated)",
+                     "alg_bytes": alg_bytes},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
