@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 
 METRIC = ("refined-Z TFLOP/s + time-to-‖ZᵀSZ−I‖≤1e-6, mixed vs FP64 path, "
           "1 MI355X")
-PEAK_TFLOPS = {"bf16": 2500.0, "fp64": 78.6}
+PEAK_TFLOPS = {"bf16": 2500.0, "fp64": 78.6, "fp32": 157.3}
 # Sources of the GEMM kernels; an HBM-traffic record in profiles/ is used only while
 # they hash to the value it was measured with.
 GEMM_SOURCES = ["paper_2404_19163_amd/csrc/gemm.hip", "paper_2404_19163_amd/csrc/gemm_tiles.inc",
@@ -55,7 +55,8 @@ def measured_traffic(kernel: str, n: int):
     if rec.get("kernel") != kernel or rec.get("n") != n or rec.get("sources_sha256") != h.hexdigest():
         return None, None
     return rec["traffic_bytes_per_dispatch"], rec.get("alg_bytes_per_dispatch")
-KCLASS_DTYPE = {"gemm_x3": "bf16", "gemm_x3_sym": "bf16", "gemm_f64": "fp64", "gemm_f64_sym": "fp64"}
+KCLASS_DTYPE = {"gemm_x3": "bf16", "gemm_x3_sym": "bf16", "gemm_f64": "fp64", "gemm_f64_sym": "fp64",
+                "gemm_hh": "bf16", "gemm_hh_sym": "bf16", "gemm_f32": "fp32", "gemm_f32_sym": "fp32"}
 
 WORKLOADS = {
     "gauss4096": dict(n=4096, sigma=1.0,
@@ -79,7 +80,9 @@ def kernel_alg_flops(cls: str, n: int) -> float:
     """Algorithmic flops of one launch at order n (no padding, no duplicated work)."""
     n = float(n)
     return {"gemm_x3": 6 * n ** 3, "gemm_x3_sym": 3 * n * n * (n + 1),
-            "gemm_f64": 2 * n ** 3, "gemm_f64_sym": n * n * (n + 1)}[cls]
+            "gemm_f64": 2 * n ** 3, "gemm_f64_sym": n * n * (n + 1),
+            "gemm_hh": 2 * n ** 3, "gemm_hh_sym": n * n * (n + 1),
+            "gemm_f32": 2 * n ** 3, "gemm_f32_sym": n * n * (n + 1)}[cls]
 
 
 def main() -> int:

@@ -57,7 +57,9 @@ extern "C" {
 enum zf_precision {
   ZF_FP64 = 0,    /* "double": every product in FP64 on the FP64 matrix cores      */
   ZF_BF16X3 = 1,  /* (h)(h)+(h)(l)+(l)(h) with BF16 halves, FP32 accumulation       */
-  ZF_FP16X3 = 2   /* reserved for the FP16-halves variant; currently ZF_ERR_ARG      */
+  ZF_FP16X3 = 2,  /* reserved for the FP16-halves variant; currently ZF_ERR_ARG      */
+  ZF_BF16 = 3,    /* (h)(h): the hi halves' product only, FP32 accumulation         */
+  ZF_FP32 = 4     /* "single": FP32 operands on the FP32 matrix cores               */
 };
 
 /* Stop rule (Sec. IV.A). */
@@ -75,9 +77,11 @@ enum zf_z0_kind {
 
 /* Refinement phase after a low-precision stop (Sec. IV.B, Algorithm 3). */
 enum zf_refine_mode {
-  ZF_REFINE_OFF = 0,       /* return the low-precision result                        */
-  ZF_REFINE_F64_DELTA = 1, /* FP64 delta and stop norm, low-precision correction      */
-  ZF_REFINE_F64_FULL = 2   /* FP64 delta and FP64 correction                         */
+  ZF_REFINE_OFF = 0,       /* return the first phase's result                         */
+  ZF_REFINE_F64_DELTA = 1, /* FP64 delta and stop norm, BF16x3 correction              */
+  ZF_REFINE_F64_FULL = 2,  /* FP64 delta and FP64 correction                          */
+  ZF_REFINE_F32 = 3        /* FP32 delta, stop norm and correction (Algorithm 3 with
+                              FP32[Z], the "+refi" of Table I in single precision)    */
 };
 
 typedef struct {
@@ -259,7 +263,9 @@ int zf_t_split(const double* a, int64_t count, uint16_t* hi, uint16_t* lo, int f
  *   A: m x k (ld k), B: nn x k (ld k), D: m x nn (ld nn) or NULL, C: m x nn (ld nn).
  *   precision ZF_FP64 runs the FP64 matrix-core kernel; ZF_BF16X3 splits A and B
  *   (as zf_t_split) and runs the (h)(h)+(h)(l)+(l)(h) kernel with FP32 accumulation
- *   (Sec. III.B).  sym != 0 requires m == nn, computes only tiles on or above the
+ *   (Sec. III.B); ZF_BF16 the (h)(h) product of the same split; ZF_FP32 rounds A
+ *   and B to FP32 and runs the FP32 matrix-core kernel (the "single" of Table I).
+ *   sym != 0 requires m == nn, computes only tiles on or above the
  *   diagonal and mirrors them (valid when A B^T is symmetric).
  *   norm_sq (host, may be NULL) receives the sum of C_ij^2 in FP64.
  */

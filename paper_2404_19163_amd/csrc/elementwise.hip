@@ -173,20 +173,38 @@ hipError_t launch_init_given(const double* Z0, int n, int np, float* z32, double
 }
 
 // FP32 master -> FP64 row-major and transposed (start of the refinement phase).
-__global__ void widen_kernel(const float* __restrict__ z32, int np, double* z64r, double* z64c) {
-  const size_t total = (size_t)np * np;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e / np), j = (int)(e % np);
-    const double v = (double)z32[e];
-    z64r[e] = v;
-    z64c[(size_t)j * np + i] = v;
+// FP32 master Z (np x np, row-major) -> any of: FP64 row-major, FP64 transposed,
+// FP32 transposed.  One 64 x 64 tile per block; the transposed copies go through a
+// padded LDS tile so that both layouts are read and written in contiguous rows.
+__global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ z32, int np,
+                                                    double* __restrict__ z64r,
+                                                    double* __restrict__ z64c,
+                                                    float* __restrict__ zc32) {
+  __shared__ float t[64][65];
+  const int T = np / 64;
+  const int i0 = (blockIdx.x / T) * 64, j0 = (blockIdx.x % T) * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    const size_t idx = (size_t)(i0 + r) * np + j0 + c;
+    const float v = z32[idx];
+    if (z64r) z64r[idx] = (double)v;
+    t[r][c] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;  // transposed row j0 + r, column i0 + c
+    const size_t idx = (size_t)(j0 + r) * np + i0 + c;
+    const float v = t[c][r];
+    if (z64c) z64c[idx] = (double)v;
+    if (zc32) zc32[idx] = v;
   }
 }
 
-hipError_t launch_widen(const float* z32, int np, double* z64r, double* z64c, hipStream_t st) {
-  const size_t total = (size_t)np * np;
-  hipLaunchKernelGGL(widen_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, z32, np, z64r, z64c);
+hipError_t launch_widen(const float* z32, int np, double* z64r, double* z64c, hipStream_t st,
+                        float* zc32) {
+  if (np % 64 != 0) return hipErrorInvalidValue;
+  const int T = np / 64;
+  hipLaunchKernelGGL(widen_kernel, dim3(T * T), dim3(256), 0, st, z32, np, z64r, z64c, zc32);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@
 namespace zf {
 // SYM is a template parameter so that the two modes are distinct kernels (and show
 // up separately in a kernel trace).
-template <int BM, int BN, int BK, int WM, int WN, bool SYM>
+template <int BM, int BN, int BK, int WM, int WN, bool SYM, bool HH>
 __global__ void __launch_bounds__(WM* WN * 64)
     gemm_x3_kernel(const u16* __restrict__ Ahi, const u16* __restrict__ Alo, int lda,
                    const u16* __restrict__ Bhi, const u16* __restrict__ Blo, int ldb, int K,
@@ -40,8 +40,29 @@ __global__ void __launch_bounds__(WM* WN * 64)
   int ti, tj;
   tile_coords(bid, tiles_n, SYM, ti, tj, gm);
   const int mode = SYM ? (ti == tj ? 2 : 1) : 0;
-  x3_tile<BM, BN, BK, WM, WN>(Ahi, Alo, lda, Bhi, Blo, ldb, K, ti * BM, tj * BN, mode, ep,
-                              blockIdx.x, lds, red);
+  x3_tile<BM, BN, BK, WM, WN, HH>(Ahi, Alo, lda, Bhi, Blo, ldb, K, ti * BM, tj * BN, mode, ep,
+                                  blockIdx.x, lds, red);
+}
+
+// FP32 matrix-core GEMM ("single"): f32_mainloop + the shared epilogue.
+template <int BM, int BN, int WM, int WN, bool SYM>
+__global__ void __launch_bounds__(WM* WN * 64)
+    gemm_f32_kernel(const float* __restrict__ A, int lda, const float* __restrict__ B, int ldb,
+                    int K, int tiles_n, int gm, EpiParams ep) {
+  using C = X3Cfg<BM, BN, 32, WM, WN>;
+  __shared__ __attribute__((aligned(16))) u16 lds[2 * C::STAGE_ELEMS];
+  __shared__ double red[C::NT / 64];
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  int ti, tj;
+  tile_coords(bid, tiles_n, SYM, ti, tj, gm);
+  const int mode = SYM ? (ti == tj ? 2 : 1) : 0;
+  X3Acc<BM, BN, 32, WM, WN> acc;
+#pragma unroll
+  for (int a = 0; a < C::FM; ++a)
+#pragma unroll
+    for (int b = 0; b < C::FN; ++b) acc[a][b] = f32x16{};
+  f32_mainloop<BM, BN, WM, WN>(A, lda, B, ldb, 0, K, ti * BM, tj * BN, lds, acc);
+  x3_epilogue<BM, BN, 32, WM, WN>(acc, ti * BM, tj * BN, mode, ep, blockIdx.x, lds, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -115,17 +136,28 @@ int f64_blocks(int M, int N, bool sym) { return grid_blocks(M, N, f64_tile_edge(
 
 int max_blocks(int M, int N) { return grid_blocks(M, N, 64, false); }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, bool HH>
 static void x3_launch(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                       int ldb, int M, int N, int K, bool sym, int blocks, const EpiParams& ep,
                       hipStream_t st) {
   if (sym)
-    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, true>), dim3(blocks), dim3(WM * WN * 64),
-                       0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, 1, ep);
+    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, true, HH>), dim3(blocks),
+                       dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, 1, ep);
   else
-    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, false>), dim3(blocks),
+    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, false, HH>), dim3(blocks),
                        dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN,
                        tile_group(M, BM), ep);
+}
+
+template <int BM, int BN, int WM, int WN>
+static void f32_launch(const float* A, int lda, const float* B, int ldb, int M, int N, int K,
+                       bool sym, int blocks, const EpiParams& ep, hipStream_t st) {
+  if (sym)
+    hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, true>), dim3(blocks), dim3(WM * WN * 64),
+                       0, st, A, lda, B, ldb, K, N / BN, 1, ep);
+  else
+    hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, false>), dim3(blocks), dim3(WM * WN * 64),
+                       0, st, A, lda, B, ldb, K, N / BN, tile_group(M, BM), ep);
 }
 
 template <int BM, int BN, int WM, int WN>
@@ -142,16 +174,42 @@ static void f64_launch(const double* A, int lda, const double* B, int ldb, int M
 
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
-                          hipStream_t st) {
+                          hipStream_t st, bool hh) {
   if (!dims_ok(M, N, K, sym)) return hipErrorInvalidValue;
   const int tile = x3_tile_edge(M, N, sym);
   const int blocks = x3_blocks(M, N, sym);
+  if (hh) {
+    if (tile == 256)
+      x3_launch<256, 256, 2, 4, true>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+    else if (tile == 128)
+      x3_launch<128, 128, 2, 2, true>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+    else
+      x3_launch<64, 64, 2, 2, true>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+  } else if (tile == 256) {
+    x3_launch<256, 256, 2, 4, false>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+  } else if (tile == 128) {
+    x3_launch<128, 128, 2, 2, false>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+  } else {
+    x3_launch<64, 64, 2, 2, false>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+  }
+  return hipGetLastError();
+}
+
+// FP32 tiles follow the BF16x3 choice (same tile bodies and occupancy).
+int f32_tile_edge(int M, int N, bool sym) { return x3_tile_edge(M, N, sym); }
+int f32_blocks(int M, int N, bool sym) { return x3_blocks(M, N, sym); }
+
+hipError_t launch_gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int N, int K,
+                           bool sym, const EpiParams& ep, hipStream_t st) {
+  if (!dims_ok(M, N, K, sym)) return hipErrorInvalidValue;
+  const int tile = f32_tile_edge(M, N, sym);
+  const int blocks = f32_blocks(M, N, sym);
   if (tile == 256)
-    x3_launch<256, 256, 2, 4>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+    f32_launch<256, 256, 2, 4>(A, lda, B, ldb, M, N, K, sym, blocks, ep, st);
   else if (tile == 128)
-    x3_launch<128, 128, 2, 2>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+    f32_launch<128, 128, 2, 2>(A, lda, B, ldb, M, N, K, sym, blocks, ep, st);
   else
-    x3_launch<64, 64, 2, 2>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+    f32_launch<64, 64, 2, 2>(A, lda, B, ldb, M, N, K, sym, blocks, ep, st);
   return hipGetLastError();
 }
 

@@ -68,8 +68,9 @@ static int pad_order(int n) { return n >= 1024 ? round_up(n, 256) : round_up(n, 
 // ---------------------------------------------------------------------------
 // per-kernel timing (HIP events on the caller's stream)
 // ---------------------------------------------------------------------------
-enum KClass { K_X3 = 0, K_X3_SYM, K_F64, K_F64_SYM, K_COUNT };
-static const char* kClassName[K_COUNT] = {"gemm_x3", "gemm_x3_sym", "gemm_f64", "gemm_f64_sym"};
+enum KClass { K_X3 = 0, K_X3_SYM, K_F64, K_F64_SYM, K_HH, K_HH_SYM, K_F32, K_F32_SYM, K_COUNT };
+static const char* kClassName[K_COUNT] = {"gemm_x3", "gemm_x3_sym", "gemm_f64", "gemm_f64_sym",
+                                          "gemm_hh", "gemm_hh_sym", "gemm_f32", "gemm_f32_sym"};
 
 struct PendingEvent {
   hipEvent_t a, b;
@@ -126,7 +127,11 @@ struct Workspace {
   u16 *zr_hi[2] = {}, *zr_lo[2] = {}, *zc_hi[2] = {}, *zc_lo[2] = {};
   u16 *at_hi = nullptr, *at_lo = nullptr, *d_hi = nullptr, *d_lo = nullptr;
   u16 *q_hi = nullptr, *q_lo = nullptr, *u_hi = nullptr, *u_lo = nullptr;
-  float* z32[2] = {};
+  float* z32[2] = {};  // FP32 master Z, row-major (BF16 and FP32 arithmetic)
+  // FP32 operands ("single", Table I)
+  bool has_f32 = false;
+  float *s32 = nullptr, *zc32[2] = {}, *a32t = nullptr, *dl32 = nullptr, *q32 = nullptr,
+        *u32 = nullptr;
   // FP64
   double *s64 = nullptr, *z64r[2] = {}, *z64c[2] = {}, *a64t = nullptr, *d64 = nullptr;
   double *q64 = nullptr, *u64 = nullptr;
@@ -165,13 +170,15 @@ static int ws_alloc(Workspace& w, T** out, size_t elems) {
   return 0;
 }
 
-static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out) {
+static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out, bool need_f32 = false) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   Workspace& w = g_ws;
-  if (w.device != dev || w.np < np || (need_x3 && !w.has_x3) || (need_f64 && !w.has_f64)) {
+  if (w.device != dev || w.np < np || (need_x3 && !w.has_x3) || (need_f64 && !w.has_f64) ||
+      (need_f32 && !w.has_f32)) {
     const bool keep_x3 = (w.device == dev) && w.has_x3;
     const bool keep_f64 = (w.device == dev) && w.has_f64;
+    const bool keep_f32 = (w.device == dev) && w.has_f32;
     const int np_new = (w.device == dev && w.np > np) ? w.np : np;
     ws_free(w);
     w.device = dev;
@@ -180,6 +187,7 @@ static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out) {
     const int tiles = max_blocks(np_new, np_new);
     w.has_x3 = need_x3 || keep_x3;
     w.has_f64 = need_f64 || keep_f64;
+    w.has_f32 = need_f32 || keep_f32;
     ZF_TRY(ws_alloc(w, &w.partials, tiles));
     ZF_TRY(ws_alloc(w, &w.err_dev, 8));
     ZF_TRY(ws_alloc(w, &w.rowsum, np_new));
@@ -207,8 +215,17 @@ static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out) {
       for (int b = 0; b < 2; ++b) {
         ZF_TRY(ws_alloc(w, &w.zc_hi[b], m));
         ZF_TRY(ws_alloc(w, &w.zc_lo[b], m));
-        ZF_TRY(ws_alloc(w, &w.z32[b], m));
       }
+    }
+    if (w.has_x3 || w.has_f32)
+      for (int b = 0; b < 2; ++b) ZF_TRY(ws_alloc(w, &w.z32[b], m));
+    if (w.has_f32) {
+      ZF_TRY(ws_alloc(w, &w.s32, m));
+      ZF_TRY(ws_alloc(w, &w.a32t, m));
+      ZF_TRY(ws_alloc(w, &w.dl32, m));
+      ZF_TRY(ws_alloc(w, &w.q32, m));
+      ZF_TRY(ws_alloc(w, &w.u32, m));
+      for (int b = 0; b < 2; ++b) ZF_TRY(ws_alloc(w, &w.zc32[b], m));
     }
     if (w.has_f64) {
       ZF_TRY(ws_alloc(w, &w.s64, m));
@@ -241,19 +258,39 @@ static EpiParams epi0(int np, int n_valid) {
 }
 
 static int gemm_x3(const u16* Ah, const u16* Al, const u16* Bh, const u16* Bl, int np, bool sym,
-                   const EpiParams& ep, hipStream_t st) {
+                   const EpiParams& ep, hipStream_t st, bool hh = false) {
   PendingEvent pe{};
   const bool prof = g_prof.on;
   if (prof) {
     pe.a = take_event();
     pe.b = take_event();
-    pe.cls = sym ? K_X3_SYM : K_X3;
-    // executed MFMA flops: 3 products of 2 * tile^2 * K per launched tile
+    pe.cls = hh ? (sym ? K_HH_SYM : K_HH) : (sym ? K_X3_SYM : K_X3);
+    // executed MFMA flops: 3 (or 1) products of 2 * tile^2 * K per launched tile
     const double t = (double)x3_tile_edge(np, np, sym);
-    pe.flops = 3.0 * 2.0 * (double)x3_blocks(np, np, sym) * t * t * (double)np;
+    pe.flops = (hh ? 1.0 : 3.0) * 2.0 * (double)x3_blocks(np, np, sym) * t * t * (double)np;
     HIP_TRY(hipEventRecord(pe.a, st));
   }
-  HIP_TRY(launch_gemm_x3(Ah, Al, np, Bh, Bl, np, np, np, np, sym, ep, st));
+  HIP_TRY(launch_gemm_x3(Ah, Al, np, Bh, Bl, np, np, np, np, sym, ep, st, hh));
+  if (prof) {
+    HIP_TRY(hipEventRecord(pe.b, st));
+    g_prof.pending.push_back(pe);
+  }
+  return 0;
+}
+
+static int gemm_f32(const float* A, const float* B, int np, bool sym, const EpiParams& ep,
+                    hipStream_t st) {
+  PendingEvent pe{};
+  const bool prof = g_prof.on;
+  if (prof) {
+    pe.a = take_event();
+    pe.b = take_event();
+    pe.cls = sym ? K_F32_SYM : K_F32;
+    const double t = (double)f32_tile_edge(np, np, sym);
+    pe.flops = 2.0 * (double)f32_blocks(np, np, sym) * t * t * (double)np;
+    HIP_TRY(hipEventRecord(pe.a, st));
+  }
+  HIP_TRY(launch_gemm_f32(A, np, B, np, np, np, np, sym, ep, st));
   if (prof) {
     HIP_TRY(hipEventRecord(pe.b, st));
     g_prof.pending.push_back(pe);
@@ -284,11 +321,19 @@ static int gemm_f64(const double* A, const double* B, int np, bool sym, const Ep
 // ---------------------------------------------------------------------------
 // the sweep
 // ---------------------------------------------------------------------------
+// Arithmetic of a sweep's residual evaluation or correction: BF16 pairs with the
+// (h)(h)+(h)(l)+(l)(h) scheme (X3) or the (h)(h) scheme (HH), FP32 ("single") or
+// FP64 matrix-core GEMMs (Table I).
+enum Arith { AR_X3 = 0, AR_HH, AR_F32, AR_F64 };
+
+static bool ar_pairs(Arith a) { return a == AR_X3 || a == AR_HH; }
+
 struct Ctx {
   Workspace* w;
   int n, np, order;
   hipStream_t st;
-  double c[8];  // c_k = C(2k,k)/4^k
+  double c[8];      // c_k = C(2k,k)/4^k
+  bool keep_pairs;  // FP32 updates also write the row-major BF16 pair (a later X3 correction)
 };
 
 static void series(int m, double* c) {
@@ -306,62 +351,84 @@ static int fetch_err(Ctx& c, int count, double* err) {
   return 0;
 }
 
-// residual evaluation of Z[cur]: writes delta (hi/lo and, if high, FP64) and Err
-static int delta_eval(Ctx& c, bool high, bool want_split, int cur, double* err) {
+// Residual evaluation of Z[cur] in arithmetic `da`, leaving delta where the correction
+// in arithmetic `ca` reads it (BF16 pair, FP32 or FP64), and Err.
+static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
   Workspace& w = *c.w;
   const int np = c.np;
-  if (!high) {
-    EpiParams e1 = epi0(np, c.n);
-    e1.ohi = w.at_hi;
-    e1.olo = w.at_lo;
-    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.s_hi, w.s_lo, np, false, e1, c.st));
-    EpiParams e2 = epi0(np, c.n);
-    e2.beta = -1.0;
-    e2.gamma = 1.0;
+  EpiParams e1 = epi0(np, c.n), e2 = epi0(np, c.n);
+  e2.beta = -1.0;
+  e2.gamma = 1.0;
+  e2.partials = w.partials;
+  if (ca != da && ar_pairs(ca)) {  // FP64 delta, BF16-pair correction
     e2.ohi = e2.othi = w.d_hi;
     e2.olo = e2.otlo = w.d_lo;
-    e2.partials = w.partials;
-    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.at_hi, w.at_lo, np, true, e2, c.st));
+  }
+  int blocks = 0;
+  if (ar_pairs(da)) {
+    const bool hh = da == AR_HH;
+    e1.ohi = w.at_hi;
+    e1.olo = w.at_lo;
+    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.s_hi, w.s_lo, np, false, e1, c.st, hh));
+    e2.ohi = e2.othi = w.d_hi;
+    e2.olo = e2.otlo = w.d_lo;
+    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.at_hi, w.at_lo, np, true, e2, c.st, hh));
+    blocks = x3_blocks(np, np, true);
+  } else if (da == AR_F32) {
+    e1.o32 = w.a32t;
+    ZF_TRY(gemm_f32(w.zc32[cur], w.s32, np, false, e1, c.st));
+    e2.o32 = e2.ot32 = w.dl32;
+    ZF_TRY(gemm_f32(w.zc32[cur], w.a32t, np, true, e2, c.st));
+    blocks = f32_blocks(np, np, true);
   } else {
-    EpiParams e1 = epi0(np, c.n);
     e1.o64 = w.a64t;
     ZF_TRY(gemm_f64(w.z64c[cur], w.s64, np, false, e1, c.st));
-    EpiParams e2 = epi0(np, c.n);
-    e2.beta = -1.0;
-    e2.gamma = 1.0;
     e2.o64 = e2.ot64 = w.d64;
-    if (want_split) {
-      e2.ohi = e2.othi = w.d_hi;
-      e2.olo = e2.otlo = w.d_lo;
-    }
-    e2.partials = w.partials;
     ZF_TRY(gemm_f64(w.z64c[cur], w.a64t, np, true, e2, c.st));
+    blocks = f64_blocks(np, np, true);
   }
-  return fetch_err(c, high ? f64_blocks(np, np, true) : x3_blocks(np, np, true), err);
+  return fetch_err(c, blocks, err);
 }
 
-// Q = sum_{k=1..m} c_k delta^k by Horner over symmetric GEMMs (m >= 2).
-// Returns the BF16 pair (x3) or FP64 matrix holding Q.
-static int build_q(Ctx& c, bool x3, bool delta64, const u16** qh, const u16** ql, const double** q64) {
+// Q = sum_{k=1..m} c_k delta^k by Horner over symmetric GEMMs (m >= 2) in arithmetic
+// `ca`; delta came from arithmetic `da` (its D term in the first Horner step is read
+// from there).  Returns the buffer holding Q in the correction's representation.
+struct QRef {
+  const u16 *hi, *lo;
+  const float* f32;
+  const double* f64;
+};
+
+static int build_q(Ctx& c, Arith da, Arith ca, QRef* q) {
   Workspace& w = *c.w;
   const int np = c.np, m = c.order;
   const u16 *bh = w.d_hi, *bl = w.d_lo;
+  const float* b32 = w.dl32;
   const double* b64 = w.d64;
   for (int k = m - 1; k >= 1; --k) {
     EpiParams e = epi0(np, c.n);
     e.alpha = c.c[k];
     e.beta = (k == m - 1) ? c.c[m] : 1.0;
-    if (delta64) e.d64 = w.d64;
-    else { e.dhi = w.d_hi; e.dlo = w.d_lo; }
+    if (da == AR_F64) e.d64 = w.d64;
+    else if (da == AR_F32) e.d32 = w.dl32;
+    else {
+      e.dhi = w.d_hi;
+      e.dlo = w.d_lo;
+    }
     const bool to_q = (k % 2) == 1;
-    if (x3) {
+    if (ar_pairs(ca)) {
       u16* oh = to_q ? w.q_hi : w.u_hi;
       u16* ol = to_q ? w.q_lo : w.u_lo;
       e.ohi = e.othi = oh;
       e.olo = e.otlo = ol;
-      ZF_TRY(gemm_x3(w.d_hi, w.d_lo, bh, bl, np, true, e, c.st));
+      ZF_TRY(gemm_x3(w.d_hi, w.d_lo, bh, bl, np, true, e, c.st, ca == AR_HH));
       bh = oh;
       bl = ol;
+    } else if (ca == AR_F32) {
+      float* o = to_q ? w.q32 : w.u32;
+      e.o32 = e.ot32 = o;
+      ZF_TRY(gemm_f32(w.dl32, b32, np, true, e, c.st));
+      b32 = o;
     } else {
       double* o = to_q ? w.q64 : w.u64;
       e.o64 = e.ot64 = o;
@@ -369,43 +436,51 @@ static int build_q(Ctx& c, bool x3, bool delta64, const u16** qh, const u16** ql
       b64 = o;
     }
   }
-  *qh = bh;
-  *ql = bl;
-  *q64 = b64;
+  q->hi = bh;
+  q->lo = bl;
+  q->f32 = b32;
+  q->f64 = b64;
   return 0;
 }
 
-// Z[cur] -> Z[cur ^ 1] = Z + Z Q
-static int update(Ctx& c, bool high, bool x3corr, int cur) {
+// Z[cur] -> Z[cur ^ 1] = Z + Z Q, Q in arithmetic `ca`; the master Z is FP64 when
+// `high` (refinement phase after an FP64 residual), else FP32.
+static int update(Ctx& c, Arith da, Arith ca, bool high, int cur) {
   Workspace& w = *c.w;
   const int np = c.np, nxt = cur ^ 1;
-  const bool x3 = !high || x3corr;
-  const u16 *qh = w.d_hi, *ql = w.d_lo;
-  const double* q64 = w.d64;
+  QRef q{w.d_hi, w.d_lo, w.dl32, w.d64};
   double beta = 1.0;
   if (c.order == 1) beta = c.c[1];  // Q = c_1 delta: fold the scale into GEMM4
-  else ZF_TRY(build_q(c, x3, high, &qh, &ql, &q64));
+  else ZF_TRY(build_q(c, da, ca, &q));
   EpiParams e = epi0(np, c.n);
   e.alpha = 1.0;
   e.beta = beta;
-  if (!high) {
-    e.d32 = w.z32[cur];
-    e.o32 = w.z32[nxt];
+  if (high) {  // FP64 master
+    e.d64 = w.z64r[cur];
+    e.o64 = w.z64r[nxt];
+    e.ot64 = w.z64c[nxt];
+    if (ar_pairs(ca)) {
+      e.ohi = w.zr_hi[nxt];
+      e.olo = w.zr_lo[nxt];
+      return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], q.hi, q.lo, np, false, e, c.st, ca == AR_HH);
+    }
+    return gemm_f64(w.z64r[cur], q.f64, np, false, e, c.st);
+  }
+  e.d32 = w.z32[cur];
+  e.o32 = w.z32[nxt];
+  if (ar_pairs(ca)) {
     e.ohi = w.zr_hi[nxt];
     e.olo = w.zr_lo[nxt];
     e.othi = w.zc_hi[nxt];
     e.otlo = w.zc_lo[nxt];
-    return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], qh, ql, np, false, e, c.st);
+    return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], q.hi, q.lo, np, false, e, c.st, ca == AR_HH);
   }
-  e.d64 = w.z64r[cur];
-  e.o64 = w.z64r[nxt];
-  e.ot64 = w.z64c[nxt];
-  if (x3corr) {
+  e.ot32 = w.zc32[nxt];
+  if (c.keep_pairs) {
     e.ohi = w.zr_hi[nxt];
     e.olo = w.zr_lo[nxt];
-    return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], qh, ql, np, false, e, c.st);
   }
-  return gemm_f64(w.z64r[cur], q64, np, false, e, c.st);
+  return gemm_f32(w.z32[cur], q.f32, np, false, e, c.st);
 }
 
 struct PhaseOut {
@@ -415,17 +490,18 @@ struct PhaseOut {
   bool capped = false;
 };
 
-static int run_phase(Ctx& c, bool high, bool x3corr, int stop_rule, int max_updates, int& cur,
-                     std::vector<double>& hist, PhaseOut& out) {
+// One phase of Algorithm 2: evaluate, stop test, update, ping-pong.
+static int run_phase(Ctx& c, Arith da, Arith ca, bool high, int stop_rule, int max_updates,
+                     int& cur, std::vector<double>& hist, PhaseOut& out) {
+  static const char* kName[4] = {"BF16x3", "BF16", "FP32", "FP64"};
   double prev = 0.0;
   for (int it = 0;; ++it) {
     double err = 0.0;
-    ZF_TRY(delta_eval(c, high, high && x3corr, cur, &err));
+    ZF_TRY(delta_eval(c, da, ca, cur, &err));
     out.evals++;
     hist.push_back(err);
     if (!isfinite(err))
-      return fail(ZF_ERR_NONFINITE, "residual norm is not finite at %s sweep %d",
-                  high ? "FP64" : "low-precision", it);
+      return fail(ZF_ERR_NONFINITE, "residual norm is not finite at %s sweep %d", kName[da], it);
     bool stop = false;
     if (it > 0) {
       if (stop_rule == ZF_STOP_MONOTONE) stop = err >= prev;
@@ -448,22 +524,25 @@ static int run_phase(Ctx& c, bool high, bool x3corr, int stop_rule, int max_upda
       out.capped = true;
       return 0;
     }
-    ZF_TRY(update(c, high, x3corr, cur));
+    ZF_TRY(update(c, da, ca, high, cur));
     cur ^= 1;
     prev = err;
   }
 }
 
 // Learned guess into buffer 0 (every layout the first phase reads): S^2 by the
-// symmetric matrix-core GEMM, features, network, acceptance on the host.  Returns 1
-// when the guess was written, 0 to fall back to the scaled identity.
-static int learned_guess(Ctx& c, const double* S, bool mixed, bool use_h, hipStream_t st) {
+// symmetric matrix-core GEMM (BF16x3 when the BF16 pairs of S exist, else FP64),
+// features, network, acceptance on the host.  Returns 1 when the guess was written,
+// 0 to fall back to the scaled identity.  mixed: write the FP32 master and the BF16
+// pairs; use_h: write the FP64 master.
+static int learned_guess(Ctx& c, const double* S, bool mixed, bool use_h, bool pairs,
+                         hipStream_t st) {
   Workspace& w = *c.w;
   const int n = c.n, np = c.np;
   if (!net_ready()) return 0;
   const double* S2d = nullptr;
   const float* S2f = nullptr;
-  if (mixed) {  // BF16x3 S^2 into the second FP32 master (free until the first update)
+  if (pairs) {  // BF16x3 S^2 into the second FP32 master (free until the first update)
     EpiParams e = epi0(np, n);
     e.o32 = e.ot32 = w.z32[1];
     ZF_TRY(gemm_x3(w.s_hi, w.s_lo, w.s_hi, w.s_lo, np, true, e, st));
@@ -488,7 +567,7 @@ static int learned_guess(Ctx& c, const double* S, bool mixed, bool use_h, hipStr
   HIP_TRY(hipMemcpyAsync(w.cg + 4, cgh, sizeof cgh, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_guess_write(S, n, S2d, S2f, np, w.cg + 4, mixed ? w.z32[0] : nullptr,
                              use_h ? w.z64r[0] : nullptr, use_h ? w.z64c[0] : nullptr, w.zr_hi[0],
-                             w.zr_lo[0], mixed ? w.zc_hi[0] : nullptr, mixed ? w.zc_lo[0] : nullptr,
+                             w.zr_lo[0], pairs ? w.zc_hi[0] : nullptr, pairs ? w.zc_lo[0] : nullptr,
                              st));
   // the host copy cgh must outlive the asynchronous copy
   HIP_TRY(hipStreamSynchronize(st));
@@ -500,23 +579,38 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   if (!S || !Z) return fail(ZF_ERR_ARG, "S and Z must be non-NULL device pointers");
   if (n <= 0) return fail(ZF_ERR_ARG, "n must be >= 1 (got %d)", n);
   if (o.order < 1 || o.order > 5) return fail(ZF_ERR_ARG, "order must be in 1..5 (got %d)", o.order);
-  if (o.precision != ZF_FP64 && o.precision != ZF_BF16X3)
+  if (o.precision != ZF_FP64 && o.precision != ZF_BF16X3 && o.precision != ZF_BF16 &&
+      o.precision != ZF_FP32)
     return fail(ZF_ERR_ARG, "precision %d is not supported", o.precision);
   if (o.stop != ZF_STOP_RATIO && o.stop != ZF_STOP_MONOTONE)
     return fail(ZF_ERR_ARG, "unknown stop rule %d", o.stop);
-  if (o.refine < ZF_REFINE_OFF || o.refine > ZF_REFINE_F64_FULL)
+  if (o.refine < ZF_REFINE_OFF || o.refine > ZF_REFINE_F32)
     return fail(ZF_ERR_ARG, "unknown refine mode %d", o.refine);
   if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(ZF_ERR_ARG, "bad hist buffer");
   if (n > 46000) return fail(ZF_ERR_ARG, "n = %d exceeds the supported maximum 46000", n);
-
   if (o.z0 != 0 && o.z0 != 1) return fail(ZF_ERR_ARG, "unknown guess kind %d", o.z0);
-  const bool mixed = o.precision != ZF_FP64;
-  const bool use_h = !mixed || o.refine != ZF_REFINE_OFF;
-  const bool x3corr = mixed && o.refine == ZF_REFINE_F64_DELTA;
+
+  // arithmetic of the two phases (Table I): the first phase in the requested
+  // precision; the refinement phase (Sec. IV.B) with an FP64 residual and a BF16x3
+  // (F64_DELTA) or FP64 (F64_FULL) correction, or entirely in FP32 (F32)
+  const bool fp64_only = o.precision == ZF_FP64;
+  const Arith la = fp64_only ? AR_F64
+                   : o.precision == ZF_BF16X3 ? AR_X3
+                   : o.precision == ZF_BF16   ? AR_HH
+                                              : AR_F32;
+  const bool refine = !fp64_only && o.refine != ZF_REFINE_OFF;
+  const Arith hd = o.refine == ZF_REFINE_F32 ? AR_F32 : AR_F64;
+  const Arith hc = o.refine == ZF_REFINE_F64_DELTA ? AR_X3 : hd;
+  const bool high = refine && hd == AR_F64;  // FP64 master in the refinement phase
   const bool learned = !Z0 && o.z0 == 1;
+  const bool need_pairs = ar_pairs(la) || (refine && ar_pairs(hc));
+  const bool need_f32 = la == AR_F32 || (refine && hd == AR_F32);
+  const bool use_h = fp64_only || high;
+  const bool mixed = !fp64_only;  // FP32 master Z in the first phase
+  const bool s_pairs = ar_pairs(la);
   const int np = pad_order(n);
   Workspace* w = nullptr;
-  ZF_TRY(ws_get(np, mixed, use_h || learned, &w));
+  ZF_TRY(ws_get(np, need_pairs, use_h || learned, &w, need_f32));
 
   Ctx c;
   c.w = w;
@@ -524,34 +618,39 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   c.np = np;
   c.order = o.order;
   c.st = st;
+  c.keep_pairs = la == AR_F32 && refine && ar_pairs(hc);
   series(o.order, c.c);
   const int max_l = o.max_sweeps > 0 ? o.max_sweeps : 100;
   const int max_h = o.max_refine > 0 ? o.max_refine : 10;
 
   // setup: operands of S, then Z0
-  HIP_TRY(launch_split_pad(S, n, n, np, mixed ? w->s_hi : nullptr, mixed ? w->s_lo : nullptr,
-                           (use_h || learned) ? w->s64 : nullptr, nullptr, false, 1, st));
+  HIP_TRY(launch_split_pad(S, n, n, np, s_pairs ? w->s_hi : nullptr, s_pairs ? w->s_lo : nullptr,
+                           (use_h || learned) ? w->s64 : nullptr,
+                           need_f32 ? w->s32 : nullptr, false, 1, st));
   int z0_used = Z0 ? ZF_Z0_GIVEN : ZF_Z0_SCALED_IDENTITY;
   int guess_flags = 0;
   if (learned) {
-    int lr = learned_guess(c, S, mixed, use_h, st);
+    int lr = learned_guess(c, S, mixed, fp64_only, s_pairs, st);
     if (lr < 0) return lr;
     if (lr == 1) z0_used = ZF_Z0_LEARNED;
     else guess_flags |= ZF_WARN_Z0_FALLBACK;
   }
   if (Z0) {
-    HIP_TRY(launch_init_given(Z0, n, np, mixed ? w->z32[0] : nullptr, use_h ? w->z64r[0] : nullptr,
-                              use_h ? w->z64c[0] : nullptr, w->zr_hi[0], w->zr_lo[0],
-                              mixed ? w->zc_hi[0] : nullptr, mixed ? w->zc_lo[0] : nullptr, st));
+    HIP_TRY(launch_init_given(Z0, n, np, mixed ? w->z32[0] : nullptr,
+                              fp64_only ? w->z64r[0] : nullptr, fp64_only ? w->z64c[0] : nullptr,
+                              w->zr_hi[0], w->zr_lo[0], s_pairs ? w->zc_hi[0] : nullptr,
+                              s_pairs ? w->zc_lo[0] : nullptr, st));
   } else if (z0_used == ZF_Z0_LEARNED) {
     // written by learned_guess
   } else {
     HIP_TRY(launch_row_abs_max(S, n, n, w->rowsum, w->g_dev, st));
     HIP_TRY(launch_init_identity(w->g_dev, n, np, mixed ? w->z32[0] : nullptr,
-                                 use_h ? w->z64r[0] : nullptr, use_h ? w->z64c[0] : nullptr,
-                                 w->zr_hi[0], w->zr_lo[0], mixed ? w->zc_hi[0] : nullptr,
-                                 mixed ? w->zc_lo[0] : nullptr, st));
+                                 fp64_only ? w->z64r[0] : nullptr,
+                                 fp64_only ? w->z64c[0] : nullptr, w->zr_hi[0], w->zr_lo[0],
+                                 s_pairs ? w->zc_hi[0] : nullptr, s_pairs ? w->zc_lo[0] : nullptr,
+                                 st));
   }
+  if (la == AR_F32) HIP_TRY(launch_widen(w->z32[0], np, nullptr, nullptr, st, w->zc32[0]));
 
   std::vector<double> h;
   int cur = 0;
@@ -559,18 +658,19 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   int flags = guess_flags;
   int rc = 0;
   if (mixed) {
-    rc = run_phase(c, false, false, o.stop, max_l, cur, h, pl);
+    rc = run_phase(c, la, la, false, o.stop, max_l, cur, h, pl);
     if (rc < 0) goto done;
     if (pl.capped) flags |= ZF_WARN_MAXSWEEPS;
-    if (use_h) {
-      HIP_TRY(launch_widen(w->z32[cur], np, w->z64r[cur], w->z64c[cur], st));
-      // the refinement phase always uses the ratio rule in FP64 (Sec. IV.B)
-      rc = run_phase(c, true, x3corr, o.stop, max_h, cur, h, ph);
+    if (refine) {
+      // Algorithm 3: Z into the refinement arithmetic, then its own ratio-stopped loop
+      if (high) HIP_TRY(launch_widen(w->z32[cur], np, w->z64r[cur], w->z64c[cur], st));
+      else if (la != AR_F32) HIP_TRY(launch_widen(w->z32[cur], np, nullptr, nullptr, st, w->zc32[cur]));
+      rc = run_phase(c, hd, hc, high, o.stop, max_h, cur, h, ph);
       if (rc < 0) goto done;
       if (ph.capped) flags |= ZF_WARN_MAXSWEEPS;
     }
   } else {
-    rc = run_phase(c, true, false, o.stop, max_l, cur, h, ph);
+    rc = run_phase(c, AR_F64, AR_F64, true, o.stop, max_l, cur, h, ph);
     if (rc < 0) goto done;
     if (ph.capped) flags |= ZF_WARN_MAXSWEEPS;
   }
@@ -590,14 +690,14 @@ done:
       res->high_evals = ph.evals;
       res->hist_len = len;
       res->flags = flags;
-      res->final_err = use_h ? ph.err : pl.err;
+      res->final_err = (fp64_only || refine) ? ph.err : pl.err;
       res->final_rms = res->final_err / sqrt((double)n);
       res->status = rc < 0 ? rc : 0;
       res->z0_used = z0_used;
     }
   }
   if (rc < 0) return rc;
-  const double fe = use_h ? ph.err : pl.err;
+  const double fe = (fp64_only || refine) ? ph.err : pl.err;
   if (!(fe < 1.0)) {
     if (res) res->status = ZF_ERR_NOT_CONVERGED;
     return fail(ZF_ERR_NOT_CONVERGED,
@@ -660,12 +760,13 @@ int zf_residual(const double* S, const double* Z, int n, double* err_f, void* st
   c.np = np;
   c.order = 2;
   c.st = st;
+  c.keep_pairs = false;
   series(2, c.c);
   HIP_TRY(launch_split_pad(S, n, n, np, nullptr, nullptr, w->s64, nullptr, false, 1, st));
   HIP_TRY(launch_init_given(Z, n, np, nullptr, w->z64r[0], w->z64c[0], w->zr_hi[0], w->zr_lo[0],
                             nullptr, nullptr, st));
   double e = 0.0;
-  ZF_TRY(delta_eval(c, true, false, 0, &e));
+  ZF_TRY(delta_eval(c, AR_F64, AR_F64, 0, &e));
   if (g_prof.on) prof_harvest();
   *err_f = e;
   g_err.clear();
@@ -687,7 +788,7 @@ void zf_release(void) {
 
 const char* zf_last_error(void) { return g_err.c_str(); }
 
-int zf_version(void) { return 2; }
+int zf_version(void) { return 3; }
 
 // ---- per-kernel timing ------------------------------------------------------
 void zf_profile_enable(int on) { g_prof.on = on != 0; }
@@ -804,7 +905,8 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
               void* stream) {
   if (!A || !B || !C || m <= 0 || nn <= 0 || k <= 0) return fail(ZF_ERR_ARG, "bad gemm arguments");
   if (sym && m != nn) return fail(ZF_ERR_ARG, "symmetric mode needs m == nn");
-  if (precision != ZF_FP64 && precision != ZF_BF16X3)
+  if (precision != ZF_FP64 && precision != ZF_BF16X3 && precision != ZF_BF16 &&
+      precision != ZF_FP32)
     return fail(ZF_ERR_ARG, "precision %d not supported", precision);
   hipStream_t st = (hipStream_t)stream;
   // pad every operand to a common square tile multiple
@@ -853,7 +955,18 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
   if (sym) ep.ot64 = c64;
   ep.partials = part;
   u16 *ah = nullptr, *al = nullptr, *bh = nullptr, *bl = nullptr;
-  if (he == hipSuccess && precision == ZF_BF16X3) {
+  const bool pairs = precision == ZF_BF16X3 || precision == ZF_BF16;
+  if (he == hipSuccess && precision == ZF_FP32) {
+    float *a32, *b32;
+    if ((rc = alloc(e * 4, (void**)&a32)) || (rc = alloc(e * 4, (void**)&b32))) {
+      cleanup();
+      return rc;
+    }
+    he = launch_split_pad(a64, np, np, np, nullptr, nullptr, nullptr, a32, false, 1, st);
+    if (he == hipSuccess)
+      he = launch_split_pad(b64, np, np, np, nullptr, nullptr, nullptr, b32, false, 1, st);
+    if (he == hipSuccess) he = launch_gemm_f32(a32, np, b32, np, np, np, np, sym != 0, ep, st);
+  } else if (he == hipSuccess && pairs) {
     if ((rc = alloc(e * 2, (void**)&ah)) || (rc = alloc(e * 2, (void**)&al)) ||
         (rc = alloc(e * 2, (void**)&bh)) || (rc = alloc(e * 2, (void**)&bl))) {
       cleanup();
@@ -861,7 +974,9 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
     }
     he = launch_split_flat(a64, (int64_t)e, ah, al, 1, st);
     if (he == hipSuccess) he = launch_split_flat(b64, (int64_t)e, bh, bl, 1, st);
-    if (he == hipSuccess) he = launch_gemm_x3(ah, al, np, bh, bl, np, np, np, np, sym != 0, ep, st);
+    if (he == hipSuccess)
+      he = launch_gemm_x3(ah, al, np, bh, bl, np, np, np, np, sym != 0, ep, st,
+                          precision == ZF_BF16);
   } else if (he == hipSuccess) {
     he = launch_gemm_f64(a64, np, b64, np, np, np, np, sym != 0, ep, st);
   }
@@ -871,7 +986,10 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
       cleanup();
       return rc;
     }
-    he = launch_norm_finalize(part, precision == ZF_BF16X3 ? x3_blocks(np, np, sym != 0) : f64_blocks(np, np, sym != 0), nrm, st);
+    const int nb = pairs ? x3_blocks(np, np, sym != 0)
+                   : precision == ZF_FP32 ? f32_blocks(np, np, sym != 0)
+                                          : f64_blocks(np, np, sym != 0);
+    he = launch_norm_finalize(part, nb, nrm, st);
   }
   if (he == hipSuccess)
     he = hipMemcpy2DAsync(C, (size_t)nn * 8, c64, (size_t)np * 8, (size_t)nn * 8, m,

@@ -120,9 +120,14 @@ int f64_tile_edge(int M, int N, bool sym);
 int f64_blocks(int M, int N, bool sym);
 int max_blocks(int M, int N);            // upper bound of the above (smallest tile edge)
 
+// hh: the (h)(h) scheme (hi halves only)
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
-                          hipStream_t st);
+                          hipStream_t st, bool hh = false);
+int f32_tile_edge(int M, int N, bool sym);
+int f32_blocks(int M, int N, bool sym);
+hipError_t launch_gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int N, int K,
+                           bool sym, const EpiParams& ep, hipStream_t st);
 hipError_t launch_gemm_f64(const double* A, int lda, const double* B, int ldb, int M, int N, int K,
                            bool sym, const EpiParams& ep, hipStream_t st);
 
@@ -140,7 +145,9 @@ hipError_t launch_init_identity(const double* g, int n, int np, float* z32, doub
 hipError_t launch_init_given(const double* Z0, int n, int np, float* z32, double* z64r,
                              double* z64c, u16* zr_hi, u16* zr_lo, u16* zc_hi, u16* zc_lo,
                              hipStream_t st);
-hipError_t launch_widen(const float* z32, int np, double* z64r, double* z64c, hipStream_t st);
+// FP32 Z -> FP64 row-major / FP64 transposed / FP32 transposed (each optional); np % 64 == 0
+hipError_t launch_widen(const float* z32, int np, double* z64r, double* z64c, hipStream_t st,
+                        float* zc32 = nullptr);
 hipError_t launch_unpad_f64(const double* src, int np, int n, double* dst, hipStream_t st);
 hipError_t launch_unpad_f32(const float* src, int np, int n, double* dst, hipStream_t st);
 hipError_t launch_norm_finalize(const double* partials, int count, double* out, hipStream_t st);

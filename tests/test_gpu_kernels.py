@@ -106,6 +106,63 @@ def test_gemm_bf16x3(zf, m, nn, k, tile, monkeypatch):
     assert np.all(np.abs(C - exact) <= (3 * u * u + 3 * k * U32) * (np.abs(A) @ np.abs(B).T) * 1.01)
 
 
+@pytest.mark.parametrize("tile", ["64", "128", "256"])
+@pytest.mark.parametrize("m,nn,k", SHAPES)
+def test_gemm_hh(zf, m, nn, k, tile, monkeypatch):
+    """(h)(h): the hi halves' product only, FP32 accumulation of exact products."""
+    monkeypatch.setenv("ZF_X3_TILE", tile)
+    rng = np.random.default_rng(m * 3 + nn + 7 * k)
+    A = rng.standard_normal((m, k))
+    B = rng.standard_normal((nn, k))
+    C, _ = zf.t_gemm("bf16", _cuda(A), _cuda(B))
+    ah, _ = O.split(A)
+    bh, _ = O.split(B)
+    ref = ah.astype(float) @ bh.astype(float).T
+    bound = 2 * k * U32 * (np.abs(ah).astype(float) @ np.abs(bh).astype(float).T)
+    assert np.all(np.abs(C.cpu().numpy() - ref) <= bound)
+
+
+@pytest.mark.parametrize("tile", ["64", "128", "256"])
+@pytest.mark.parametrize("m,nn,k", SHAPES)
+def test_gemm_fp32(zf, m, nn, k, tile, monkeypatch):
+    """FP32 operands on the FP32 matrix cores (K traversed in a permuted order): within
+    the FP32 dot-product bound of the product of the FP32-rounded operands."""
+    monkeypatch.setenv("ZF_X3_TILE", tile)
+    rng = np.random.default_rng(m * 11 + nn + 5 * k)
+    A = rng.standard_normal((m, k)) * np.exp(rng.uniform(-3, 3, (m, 1)))
+    B = rng.standard_normal((nn, k))
+    C, _ = zf.t_gemm("fp32", _cuda(A), _cuda(B))
+    a32 = O.to_fp32(A).astype(float)
+    b32 = O.to_fp32(B).astype(float)
+    ref = a32 @ b32.T
+    bound = 2 * k * U32 * (np.abs(a32) @ np.abs(b32).T)
+    assert np.all(np.abs(C.cpu().numpy() - ref) <= bound)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,k", [(128, 128), (300, 200), (1000, 256)])
+def test_gemm_symmetric_fp32_hh(zf, prec, n, k):
+    rng = np.random.default_rng(n + 3 * k)
+    A = rng.standard_normal((n, k)) / math.sqrt(k)
+    M = rng.standard_normal((k, k))
+    B = A @ ((M + M.T) / 2)
+    C, nsq = zf.t_gemm(prec, _cuda(A), _cuda(B), sym=True, beta=-1.0, gamma=1.0)
+    C = C.cpu().numpy()
+    assert np.array_equal(C, C.T)
+    if prec == "fp32":
+        a, b = O.to_fp32(A).astype(float), O.to_fp32(B).astype(float)
+        bound = 2 * k * U32 * (np.abs(a) @ np.abs(b).T) + 4 * U32
+    else:
+        a, _ = O.split(A)
+        b, _ = O.split(B)
+        a, b = a.astype(float), b.astype(float)
+        bound = 2 * k * U32 * (np.abs(a) @ np.abs(b).T) + 4 * U32
+    ref = np.eye(n) - a @ b.T
+    up = np.triu(np.ones((n, n), dtype=bool))
+    assert np.all(np.abs(C - ref)[up] <= bound[up])
+    assert nsq == pytest.approx(math.fsum((C * C).ravel().tolist()), rel=1e-12)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp64-t128", "bf16x3", "bf16x3-t128", "bf16x3-t64"])
 @pytest.mark.parametrize("n,k", [(128, 128), (300, 200), (640, 512), (129, 64), (1000, 256),
                                  (2048, 128)])
