@@ -52,7 +52,7 @@ def measured_traffic(kernel: str, n: int):
                 h.update(fh.read())
     except (OSError, AttributeError, ValueError):
         return None, None
-    if rec.get("kernel") != kernel or rec.get("n") != n or rec.get("sources_sha256") != h.hexdigest():
+    if not isinstance(rec, dict) or rec.get("kernel") != kernel or rec.get("n") != n or rec.get("sources_sha256") != h.hexdigest():
         return None, None
     return rec["traffic_bytes_per_dispatch"], rec.get("alg_bytes_per_dispatch")
 KCLASS_DTYPE = {"gemm_x3": "bf16", "gemm_x3_sym": "bf16", "gemm_f64": "fp64", "gemm_f64_sym": "fp64",
@@ -91,7 +91,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gauss4096",
-                    choices=sorted(WORKLOADS) + ["batched512", "md3000"])
+                    choices=sorted(WORKLOADS) + ["batched512", "md3000", "table1"])
+    ap.add_argument("--n", type=int, default=4096, help="order of the table1 workload")
     ap.add_argument("--frames", type=int, default=64, help="frames of the md3000 workload")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--order", type=int, default=2)
@@ -124,6 +125,8 @@ def main() -> int:
         return bench_batched(args)
     if args.workload == "md3000":
         return bench_md(args)
+    if args.workload == "table1":
+        return bench_table1(args)
     wl = WORKLOADS[args.workload]
     n = wl["n"]
     t0 = time.perf_counter()
@@ -174,7 +177,7 @@ def main() -> int:
                    "share": round(v[1] / max(mixed_s * 1e3 * args.steps, 1e-9), 4),
                    "alg_tflops": round(kernel_alg_flops(k, n) / (v[1] / 1e3 / v[0]) / 1e12, 2)
                    if v[0] else None}
-               for k, v in prof.items()}
+               for k, v in prof.items() if v[0]}
 
     # ---- FP64 path -------------------------------------------------------
     fp64 = None
@@ -251,6 +254,75 @@ def main() -> int:
                      "alg_bytes": alg_bytes},
         "cpu_baseline": cpu,
     }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_table1(args) -> int:
+    """The schemes of the paper's Table I on its synthetic family (Sec. V.A): S =
+    sym(exp(-|i-j|/2) sin(i+1)) shifted to lowest eigenvalue 0.5, Z0 = S^(-1/2) + 0.005 U.
+    Per scheme: time per solve, updates, residual evaluations, ||X - I||_2 and the RMS
+    ||Z^T S Z - I||_F / sqrt(N) of the returned Z (both evaluated in FP64 outside the
+    timed region)."""
+    import numpy as np
+    import torch
+
+    from paper_2404_19163_amd import inputs, zf
+
+    n = args.n
+    t0 = time.perf_counter()
+    S_np = inputs.paper_synthetic(n, 0.5)
+    w, V = np.linalg.eigh(S_np)
+    Z0_np = (V / np.sqrt(w)) @ V.T + 0.005 * inputs.uniform_noise(n, args.seed)
+    print(f"[bench] synthetic S and Z0 (N={n}) in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    S = torch.from_numpy(S_np).to("cuda:0")
+    Z0 = torch.from_numpy(Z0_np).to("cuda:0")
+    out = torch.empty_like(S)
+    eye = torch.eye(n, dtype=torch.float64, device="cuda:0")
+    schemes = [("double", "fp64", "off"), ("single", "fp32", "off"), ("(h)(h)", "bf16", "off"),
+               ("(h)(h)+refi", "bf16", "f32"), ("(h)(h)+(h)(l)+(l)(h)", "bf16x3", "off"),
+               ("(h)(h)+(h)(l)+(l)(h)+refi", "bf16x3", "f64_full"),
+               ("(h)(h)+(h)(l)+(l)(h)+refi(delta)", "bf16x3", "f64_delta")]
+    rows = {}
+    for name, prec, ref in schemes:
+        for _ in range(args.warmup):
+            zf.refine(S, Z0, precision=prec, refine=ref, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = None
+        for _ in range(args.steps):
+            r = zf.refine(S, Z0, precision=prec, refine=ref, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        X = out.T @ (S @ out)
+        e2 = float(torch.linalg.eigvalsh((X + X.T) / 2 - eye).abs().max())
+        rms = float(torch.linalg.norm(X - eye)) / math.sqrt(n)
+        rows[name] = {"ms": round(ms, 3), "updates": r.iters, "evals": [r.low_evals, r.high_evals],
+                      "err2": e2, "rms": rms}
+        print(f"[bench] {name}: {ms:.2f} ms, err2 {e2:.2e}", file=sys.stderr, flush=True)
+    # context (Fig. runtime): S^(-1/2) by dense diagonalization on the GPU (torch.linalg.eigh,
+    # the ROCm solver), timed the same way
+    def diag():
+        w_, V_ = torch.linalg.eigh(S)
+        return (V_ * w_.rsqrt()) @ V_.T
+    for _ in range(args.warmup):
+        diag()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Zd = diag()
+    torch.cuda.synchronize()
+    X = Zd.T @ (S @ Zd)
+    rows["diagonalization (eigh, FP64)"] = {
+        "ms": round((time.perf_counter() - t0) / args.steps * 1e3, 3),
+        "err2": float(torch.linalg.eigvalsh((X + X.T) / 2 - eye).abs().max())}
+    line = {"metric": "Table I schemes on the paper's synthetic family: time per solve and "
+                      "||Z^T S Z - I||_2", "n": n, "unit": "ms", "higher_is_better": False,
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
+            "config": {"workload": f"Sec. V.A synthetic S (gamma 0.5), N={n}, Z0 = S^-1/2 + 0.005 U",
+                       "seed": args.seed},
+            "schemes": rows}
     print(json.dumps(line), flush=True)
     return 0
 
