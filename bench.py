@@ -56,7 +56,9 @@ def measured_traffic(kernel: str, n: int):
         return None, None
     return rec["traffic_bytes_per_dispatch"], rec.get("alg_bytes_per_dispatch")
 KCLASS_DTYPE = {"gemm_x3": "bf16", "gemm_x3_sym": "bf16", "gemm_f64": "fp64", "gemm_f64_sym": "fp64",
-                "gemm_hh": "bf16", "gemm_hh_sym": "bf16", "gemm_f32": "fp32", "gemm_f32_sym": "fp32"}
+                "gemm_hh": "bf16", "gemm_hh_sym": "bf16", "gemm_f32": "fp32", "gemm_f32_sym": "fp32",
+                "gemm_x3f16": "bf16", "gemm_x3f16_sym": "bf16", "gemm_hhf16": "bf16",
+                "gemm_hhf16_sym": "bf16"}
 
 WORKLOADS = {
     "gauss4096": dict(n=4096, sigma=1.0,
@@ -82,7 +84,9 @@ def kernel_alg_flops(cls: str, n: int) -> float:
     return {"gemm_x3": 6 * n ** 3, "gemm_x3_sym": 3 * n * n * (n + 1),
             "gemm_f64": 2 * n ** 3, "gemm_f64_sym": n * n * (n + 1),
             "gemm_hh": 2 * n ** 3, "gemm_hh_sym": n * n * (n + 1),
-            "gemm_f32": 2 * n ** 3, "gemm_f32_sym": n * n * (n + 1)}[cls]
+            "gemm_f32": 2 * n ** 3, "gemm_f32_sym": n * n * (n + 1),
+            "gemm_x3f16": 6 * n ** 3, "gemm_x3f16_sym": 3 * n * n * (n + 1),
+            "gemm_hhf16": 2 * n ** 3, "gemm_hhf16_sym": n * n * (n + 1)}[cls]
 
 
 def main() -> int:
@@ -280,10 +284,14 @@ def bench_table1(args) -> int:
     Z0 = torch.from_numpy(Z0_np).to("cuda:0")
     out = torch.empty_like(S)
     eye = torch.eye(n, dtype=torch.float64, device="cuda:0")
-    schemes = [("double", "fp64", "off"), ("single", "fp32", "off"), ("(h)(h)", "bf16", "off"),
-               ("(h)(h)+refi", "bf16", "f32"), ("(h)(h)+(h)(l)+(l)(h)", "bf16x3", "off"),
-               ("(h)(h)+(h)(l)+(l)(h)+refi", "bf16x3", "f64_full"),
-               ("(h)(h)+(h)(l)+(l)(h)+refi(delta)", "bf16x3", "f64_delta")]
+    schemes = [("double", "fp64", "off"), ("single", "fp32", "off"),
+               ("(h)(h) BF16", "bf16", "off"), ("(h)(h)+refi BF16", "bf16", "f32"),
+               ("(h)(h)+(h)(l)+(l)(h) BF16", "bf16x3", "off"),
+               ("(h)(h)+(h)(l)+(l)(h)+refi BF16", "bf16x3", "f64_full"),
+               ("(h)(h)+(h)(l)+(l)(h)+refi(delta) BF16", "bf16x3", "f64_delta"),
+               ("(h)(h) FP16", "fp16", "off"), ("(h)(h)+refi FP16", "fp16", "f32"),
+               ("(h)(h)+(h)(l)+(l)(h) FP16", "fp16x3", "off"),
+               ("(h)(h)+(h)(l)+(l)(h)+refi(delta) FP16", "fp16x3", "f64_delta")]
     rows = {}
     for name, prec, ref in schemes:
         for _ in range(args.warmup):

@@ -57,9 +57,12 @@ extern "C" {
 enum zf_precision {
   ZF_FP64 = 0,    /* "double": every product in FP64 on the FP64 matrix cores      */
   ZF_BF16X3 = 1,  /* (h)(h)+(h)(l)+(l)(h) with BF16 halves, FP32 accumulation       */
-  ZF_FP16X3 = 2,  /* reserved for the FP16-halves variant; currently ZF_ERR_ARG      */
+  ZF_FP16X3 = 2,  /* (h)(h)+(h)(l)+(l)(h) with FP16 halves (the paper's Eq. splitStyle);
+                     delta and Q are split after a power-of-two scale to FP16's range;
+                     S and Z entries must stay within FP16's range (|x| < 65504)       */
   ZF_BF16 = 3,    /* (h)(h): the hi halves' product only, FP32 accumulation         */
-  ZF_FP32 = 4     /* "single": FP32 operands on the FP32 matrix cores               */
+  ZF_FP32 = 4,    /* "single": FP32 operands on the FP32 matrix cores               */
+  ZF_FP16 = 5     /* (h)(h) with FP16 halves                                        */
 };
 
 /* Stop rule (Sec. IV.A). */

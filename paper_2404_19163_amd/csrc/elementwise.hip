@@ -173,13 +173,17 @@ hipError_t launch_init_given(const double* Z0, int n, int np, float* z32, double
 }
 
 // FP32 master -> FP64 row-major and transposed (start of the refinement phase).
-// FP32 master Z (np x np, row-major) -> any of: FP64 row-major, FP64 transposed,
-// FP32 transposed.  One 64 x 64 tile per block; the transposed copies go through a
-// padded LDS tile so that both layouts are read and written in contiguous rows.
+// FP32 matrix X (np x np, row-major) -> any of: FP64 row-major, FP64 transposed,
+// FP32 transposed, and 16-bit pairs (format fmt) of scale * X, row-major and/or
+// transposed.  scale is a power of two (exact).  One 64 x 64 tile per block; the
+// transposed copies go through a padded LDS tile so that both layouts are read
+// and written in contiguous rows.
 __global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ z32, int np,
                                                     double* __restrict__ z64r,
                                                     double* __restrict__ z64c,
-                                                    float* __restrict__ zc32) {
+                                                    float* __restrict__ zc32, u16* __restrict__ prh,
+                                                    u16* __restrict__ prl, u16* __restrict__ pch,
+                                                    u16* __restrict__ pcl, float scale, int fmt) {
   __shared__ float t[64][65];
   const int T = np / 64;
   const int i0 = (blockIdx.x / T) * 64, j0 = (blockIdx.x % T) * 64;
@@ -188,6 +192,12 @@ __global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ z3
     const size_t idx = (size_t)(i0 + r) * np + j0 + c;
     const float v = z32[idx];
     if (z64r) z64r[idx] = (double)v;
+    if (prh) {
+      u16 h, l;
+      split_pair(v * scale, h, l, fmt);
+      prh[idx] = h;
+      prl[idx] = l;
+    }
     t[r][c] = v;
   }
   __syncthreads();
@@ -197,14 +207,22 @@ __global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ z3
     const float v = t[c][r];
     if (z64c) z64c[idx] = (double)v;
     if (zc32) zc32[idx] = v;
+    if (pch) {
+      u16 h, l;
+      split_pair(v * scale, h, l, fmt);
+      pch[idx] = h;
+      pcl[idx] = l;
+    }
   }
 }
 
 hipError_t launch_widen(const float* z32, int np, double* z64r, double* z64c, hipStream_t st,
-                        float* zc32) {
+                        float* zc32, u16* prh, u16* prl, u16* pch, u16* pcl, float scale,
+                        int fmt) {
   if (np % 64 != 0) return hipErrorInvalidValue;
   const int T = np / 64;
-  hipLaunchKernelGGL(widen_kernel, dim3(T * T), dim3(256), 0, st, z32, np, z64r, z64c, zc32);
+  hipLaunchKernelGGL(widen_kernel, dim3(T * T), dim3(256), 0, st, z32, np, z64r, z64c, zc32, prh,
+                     prl, pch, pcl, scale, fmt);
   return hipGetLastError();
 }
 

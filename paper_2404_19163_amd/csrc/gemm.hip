@@ -28,7 +28,7 @@
 namespace zf {
 // SYM is a template parameter so that the two modes are distinct kernels (and show
 // up separately in a kernel trace).
-template <int BM, int BN, int BK, int WM, int WN, bool SYM, bool HH>
+template <int BM, int BN, int BK, int WM, int WN, bool SYM, int PM>
 __global__ void __launch_bounds__(WM* WN * 64)
     gemm_x3_kernel(const u16* __restrict__ Ahi, const u16* __restrict__ Alo, int lda,
                    const u16* __restrict__ Bhi, const u16* __restrict__ Blo, int ldb, int K,
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(WM* WN * 64)
   int ti, tj;
   tile_coords(bid, tiles_n, SYM, ti, tj, gm);
   const int mode = SYM ? (ti == tj ? 2 : 1) : 0;
-  x3_tile<BM, BN, BK, WM, WN, HH>(Ahi, Alo, lda, Bhi, Blo, ldb, K, ti * BM, tj * BN, mode, ep,
+  x3_tile<BM, BN, BK, WM, WN, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, K, ti * BM, tj * BN, mode, ep,
                                   blockIdx.x, lds, red);
 }
 
@@ -136,15 +136,15 @@ int f64_blocks(int M, int N, bool sym) { return grid_blocks(M, N, f64_tile_edge(
 
 int max_blocks(int M, int N) { return grid_blocks(M, N, 64, false); }
 
-template <int BM, int BN, int WM, int WN, bool HH>
+template <int BM, int BN, int WM, int WN, int PM>
 static void x3_launch(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                       int ldb, int M, int N, int K, bool sym, int blocks, const EpiParams& ep,
                       hipStream_t st) {
   if (sym)
-    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, true, HH>), dim3(blocks),
+    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, true, PM>), dim3(blocks),
                        dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, 1, ep);
   else
-    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, false, HH>), dim3(blocks),
+    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, false, PM>), dim3(blocks),
                        dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN,
                        tile_group(M, BM), ep);
 }
@@ -172,25 +172,36 @@ static void f64_launch(const double* A, int lda, const double* B, int ldb, int M
                        ep);
 }
 
+template <int PM>
+static void x3_dispatch(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
+                        int ldb, int M, int N, int K, bool sym, int tile, int blocks,
+                        const EpiParams& ep, hipStream_t st) {
+  if (tile == 256)
+    x3_launch<256, 256, 2, 4, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+  else if (tile == 128)
+    x3_launch<128, 128, 2, 2, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+  else
+    x3_launch<64, 64, 2, 2, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+}
+
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
-                          hipStream_t st, bool hh) {
-  if (!dims_ok(M, N, K, sym)) return hipErrorInvalidValue;
+                          hipStream_t st, int pm) {
+  if (!dims_ok(M, N, K, sym) || pm < 0 || pm > 3) return hipErrorInvalidValue;
   const int tile = x3_tile_edge(M, N, sym);
   const int blocks = x3_blocks(M, N, sym);
-  if (hh) {
-    if (tile == 256)
-      x3_launch<256, 256, 2, 4, true>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
-    else if (tile == 128)
-      x3_launch<128, 128, 2, 2, true>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
-    else
-      x3_launch<64, 64, 2, 2, true>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
-  } else if (tile == 256) {
-    x3_launch<256, 256, 2, 4, false>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
-  } else if (tile == 128) {
-    x3_launch<128, 128, 2, 2, false>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
-  } else {
-    x3_launch<64, 64, 2, 2, false>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+  switch (pm) {
+    case PM_X3:
+      x3_dispatch<PM_X3>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st);
+      break;
+    case PM_HH:
+      x3_dispatch<PM_HH>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st);
+      break;
+    case PM_X3F16:
+      x3_dispatch<PM_X3F16>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st);
+      break;
+    default:
+      x3_dispatch<PM_HHF16>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st);
   }
   return hipGetLastError();
 }

@@ -68,9 +68,13 @@ static int pad_order(int n) { return n >= 1024 ? round_up(n, 256) : round_up(n, 
 // ---------------------------------------------------------------------------
 // per-kernel timing (HIP events on the caller's stream)
 // ---------------------------------------------------------------------------
-enum KClass { K_X3 = 0, K_X3_SYM, K_F64, K_F64_SYM, K_HH, K_HH_SYM, K_F32, K_F32_SYM, K_COUNT };
-static const char* kClassName[K_COUNT] = {"gemm_x3", "gemm_x3_sym", "gemm_f64", "gemm_f64_sym",
-                                          "gemm_hh", "gemm_hh_sym", "gemm_f32", "gemm_f32_sym"};
+enum KClass {
+  K_X3 = 0, K_X3_SYM, K_F64, K_F64_SYM, K_HH, K_HH_SYM, K_F32, K_F32_SYM, K_X3F16, K_X3F16_SYM,
+  K_HHF16, K_HHF16_SYM, K_COUNT
+};
+static const char* kClassName[K_COUNT] = {
+    "gemm_x3", "gemm_x3_sym", "gemm_f64", "gemm_f64_sym", "gemm_hh", "gemm_hh_sym",
+    "gemm_f32", "gemm_f32_sym", "gemm_x3f16", "gemm_x3f16_sym", "gemm_hhf16", "gemm_hhf16_sym"};
 
 struct PendingEvent {
   hipEvent_t a, b;
@@ -258,19 +262,21 @@ static EpiParams epi0(int np, int n_valid) {
 }
 
 static int gemm_x3(const u16* Ah, const u16* Al, const u16* Bh, const u16* Bl, int np, bool sym,
-                   const EpiParams& ep, hipStream_t st, bool hh = false) {
+                   const EpiParams& ep, hipStream_t st, int pm = PM_X3) {
   PendingEvent pe{};
   const bool prof = g_prof.on;
   if (prof) {
+    static const int cls[4][2] = {{K_X3, K_X3_SYM}, {K_HH, K_HH_SYM}, {K_X3F16, K_X3F16_SYM},
+                                  {K_HHF16, K_HHF16_SYM}};
     pe.a = take_event();
     pe.b = take_event();
-    pe.cls = hh ? (sym ? K_HH_SYM : K_HH) : (sym ? K_X3_SYM : K_X3);
+    pe.cls = cls[pm][sym ? 1 : 0];
     // executed MFMA flops: 3 (or 1) products of 2 * tile^2 * K per launched tile
     const double t = (double)x3_tile_edge(np, np, sym);
-    pe.flops = (hh ? 1.0 : 3.0) * 2.0 * (double)x3_blocks(np, np, sym) * t * t * (double)np;
+    pe.flops = ((pm & PM_HH) ? 1.0 : 3.0) * 2.0 * (double)x3_blocks(np, np, sym) * t * t * (double)np;
     HIP_TRY(hipEventRecord(pe.a, st));
   }
-  HIP_TRY(launch_gemm_x3(Ah, Al, np, Bh, Bl, np, np, np, np, sym, ep, st, hh));
+  HIP_TRY(launch_gemm_x3(Ah, Al, np, Bh, Bl, np, np, np, np, sym, ep, st, pm));
   if (prof) {
     HIP_TRY(hipEventRecord(pe.b, st));
     g_prof.pending.push_back(pe);
@@ -324,9 +330,15 @@ static int gemm_f64(const double* A, const double* B, int np, bool sym, const Ep
 // Arithmetic of a sweep's residual evaluation or correction: BF16 pairs with the
 // (h)(h)+(h)(l)+(l)(h) scheme (X3) or the (h)(h) scheme (HH), FP32 ("single") or
 // FP64 matrix-core GEMMs (Table I).
-enum Arith { AR_X3 = 0, AR_HH, AR_F32, AR_F64 };
+enum Arith { AR_X3 = 0, AR_HH, AR_F32, AR_F64, AR_X3F16, AR_HHF16 };
 
-static bool ar_pairs(Arith a) { return a == AR_X3 || a == AR_HH; }
+static bool ar_pairs(Arith a) {
+  return a == AR_X3 || a == AR_HH || a == AR_X3F16 || a == AR_HHF16;
+}
+static bool ar_f16(Arith a) { return a == AR_X3F16 || a == AR_HHF16; }
+static int ar_pm(Arith a) {
+  return a == AR_HH ? PM_HH : a == AR_X3F16 ? PM_X3F16 : a == AR_HHF16 ? PM_HHF16 : PM_X3;
+}
 
 struct Ctx {
   Workspace* w;
@@ -334,6 +346,7 @@ struct Ctx {
   hipStream_t st;
   double c[8];      // c_k = C(2k,k)/4^k
   bool keep_pairs;  // FP32 updates also write the row-major BF16 pair (a later X3 correction)
+  double sigma;     // power-of-two scale of the FP16 delta pairs (FP16 halves only)
 };
 
 static void series(int m, double* c) {
@@ -352,7 +365,10 @@ static int fetch_err(Ctx& c, int count, double* err) {
 }
 
 // Residual evaluation of Z[cur] in arithmetic `da`, leaving delta where the correction
-// in arithmetic `ca` reads it (BF16 pair, FP32 or FP64), and Err.
+// in arithmetic `ca` reads it (BF16 pair, FP32 or FP64), and Err.  With FP16 halves
+// delta is formed in FP32 and, once Err is known, split into FP16 pairs of sigma *
+// delta with sigma = 2^-floor(log2 Err) (|sigma delta_ij| <= 2: delta's entries fall
+// below FP16's normal range as Z converges).
 static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
   Workspace& w = *c.w;
   const int np = c.np;
@@ -366,13 +382,19 @@ static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
   }
   int blocks = 0;
   if (ar_pairs(da)) {
-    const bool hh = da == AR_HH;
+    const int pm = ar_pm(da);
+    const int fmt = ar_f16(da) ? PAIR_F16 : PAIR_BF16;
     e1.ohi = w.at_hi;
     e1.olo = w.at_lo;
-    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.s_hi, w.s_lo, np, false, e1, c.st, hh));
-    e2.ohi = e2.othi = w.d_hi;
-    e2.olo = e2.otlo = w.d_lo;
-    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.at_hi, w.at_lo, np, true, e2, c.st, hh));
+    e1.pair_fmt = fmt;
+    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.s_hi, w.s_lo, np, false, e1, c.st, pm));
+    if (ar_f16(da)) {
+      e2.o32 = e2.ot32 = w.dl32;
+    } else {
+      e2.ohi = e2.othi = w.d_hi;
+      e2.olo = e2.otlo = w.d_lo;
+    }
+    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.at_hi, w.at_lo, np, true, e2, c.st, pm));
     blocks = x3_blocks(np, np, true);
   } else if (da == AR_F32) {
     e1.o32 = w.a32t;
@@ -387,7 +409,13 @@ static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
     ZF_TRY(gemm_f64(w.z64c[cur], w.a64t, np, true, e2, c.st));
     blocks = f64_blocks(np, np, true);
   }
-  return fetch_err(c, blocks, err);
+  ZF_TRY(fetch_err(c, blocks, err));
+  if (ar_f16(da) && isfinite(*err)) {
+    c.sigma = (*err > 0.0) ? ldexp(1.0, -(int)floor(log2(*err))) : 1.0;
+    HIP_TRY(launch_widen(w.dl32, np, nullptr, nullptr, c.st, nullptr, w.d_hi, w.d_lo, nullptr,
+                         nullptr, (float)c.sigma, PAIR_F16));
+  }
+  return 0;
 }
 
 // Q = sum_{k=1..m} c_k delta^k by Horner over symmetric GEMMs (m >= 2) in arithmetic
@@ -405,12 +433,15 @@ static int build_q(Ctx& c, Arith da, Arith ca, QRef* q) {
   const u16 *bh = w.d_hi, *bl = w.d_lo;
   const float* b32 = w.dl32;
   const double* b64 = w.d64;
+  // FP16 halves carry sigma * Q: U~_k = c_k sigma delta + (1/sigma) delta~ U~_{k+1}
+  const bool f16 = ar_f16(ca);
+  const double sg = f16 ? c.sigma : 1.0;
   for (int k = m - 1; k >= 1; --k) {
     EpiParams e = epi0(np, c.n);
-    e.alpha = c.c[k];
-    e.beta = (k == m - 1) ? c.c[m] : 1.0;
+    e.alpha = c.c[k] * sg;
+    e.beta = ((k == m - 1) ? c.c[m] : 1.0) / sg;
     if (da == AR_F64) e.d64 = w.d64;
-    else if (da == AR_F32) e.d32 = w.dl32;
+    else if (da == AR_F32 || f16) e.d32 = w.dl32;
     else {
       e.dhi = w.d_hi;
       e.dlo = w.d_lo;
@@ -421,7 +452,8 @@ static int build_q(Ctx& c, Arith da, Arith ca, QRef* q) {
       u16* ol = to_q ? w.q_lo : w.u_lo;
       e.ohi = e.othi = oh;
       e.olo = e.otlo = ol;
-      ZF_TRY(gemm_x3(w.d_hi, w.d_lo, bh, bl, np, true, e, c.st, ca == AR_HH));
+      e.pair_fmt = f16 ? PAIR_F16 : PAIR_BF16;
+      ZF_TRY(gemm_x3(w.d_hi, w.d_lo, bh, bl, np, true, e, c.st, ar_pm(ca)));
       bh = oh;
       bl = ol;
     } else if (ca == AR_F32) {
@@ -452,9 +484,11 @@ static int update(Ctx& c, Arith da, Arith ca, bool high, int cur) {
   double beta = 1.0;
   if (c.order == 1) beta = c.c[1];  // Q = c_1 delta: fold the scale into GEMM4
   else ZF_TRY(build_q(c, da, ca, &q));
+  if (ar_f16(ca)) beta /= c.sigma;  // the pairs hold sigma * Q
   EpiParams e = epi0(np, c.n);
   e.alpha = 1.0;
   e.beta = beta;
+  e.pair_fmt = ar_f16(ca) ? PAIR_F16 : PAIR_BF16;
   if (high) {  // FP64 master
     e.d64 = w.z64r[cur];
     e.o64 = w.z64r[nxt];
@@ -462,7 +496,7 @@ static int update(Ctx& c, Arith da, Arith ca, bool high, int cur) {
     if (ar_pairs(ca)) {
       e.ohi = w.zr_hi[nxt];
       e.olo = w.zr_lo[nxt];
-      return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], q.hi, q.lo, np, false, e, c.st, ca == AR_HH);
+      return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], q.hi, q.lo, np, false, e, c.st, ar_pm(ca));
     }
     return gemm_f64(w.z64r[cur], q.f64, np, false, e, c.st);
   }
@@ -473,7 +507,7 @@ static int update(Ctx& c, Arith da, Arith ca, bool high, int cur) {
     e.olo = w.zr_lo[nxt];
     e.othi = w.zc_hi[nxt];
     e.otlo = w.zc_lo[nxt];
-    return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], q.hi, q.lo, np, false, e, c.st, ca == AR_HH);
+    return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], q.hi, q.lo, np, false, e, c.st, ar_pm(ca));
   }
   e.ot32 = w.zc32[nxt];
   if (c.keep_pairs) {
@@ -535,7 +569,7 @@ static int run_phase(Ctx& c, Arith da, Arith ca, bool high, int stop_rule, int m
 // features, network, acceptance on the host.  Returns 1 when the guess was written,
 // 0 to fall back to the scaled identity.  mixed: write the FP32 master and the BF16
 // pairs; use_h: write the FP64 master.
-static int learned_guess(Ctx& c, const double* S, bool mixed, bool use_h, bool pairs,
+static int learned_guess(Ctx& c, const double* S, bool mixed, bool use_h, bool pairs, int pm,
                          hipStream_t st) {
   Workspace& w = *c.w;
   const int n = c.n, np = c.np;
@@ -545,7 +579,7 @@ static int learned_guess(Ctx& c, const double* S, bool mixed, bool use_h, bool p
   if (pairs) {  // BF16x3 S^2 into the second FP32 master (free until the first update)
     EpiParams e = epi0(np, n);
     e.o32 = e.ot32 = w.z32[1];
-    ZF_TRY(gemm_x3(w.s_hi, w.s_lo, w.s_hi, w.s_lo, np, true, e, st));
+    ZF_TRY(gemm_x3(w.s_hi, w.s_lo, w.s_hi, w.s_lo, np, true, e, st, pm));
     S2f = w.z32[1];
   } else {  // FP64 S^2 into A^T's buffer (free until the first residual)
     EpiParams e = epi0(np, n);
@@ -579,8 +613,7 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   if (!S || !Z) return fail(ZF_ERR_ARG, "S and Z must be non-NULL device pointers");
   if (n <= 0) return fail(ZF_ERR_ARG, "n must be >= 1 (got %d)", n);
   if (o.order < 1 || o.order > 5) return fail(ZF_ERR_ARG, "order must be in 1..5 (got %d)", o.order);
-  if (o.precision != ZF_FP64 && o.precision != ZF_BF16X3 && o.precision != ZF_BF16 &&
-      o.precision != ZF_FP32)
+  if (o.precision < ZF_FP64 || o.precision > ZF_FP16)
     return fail(ZF_ERR_ARG, "precision %d is not supported", o.precision);
   if (o.stop != ZF_STOP_RATIO && o.stop != ZF_STOP_MONOTONE)
     return fail(ZF_ERR_ARG, "unknown stop rule %d", o.stop);
@@ -597,6 +630,8 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   const Arith la = fp64_only ? AR_F64
                    : o.precision == ZF_BF16X3 ? AR_X3
                    : o.precision == ZF_BF16   ? AR_HH
+                   : o.precision == ZF_FP16X3 ? AR_X3F16
+                   : o.precision == ZF_FP16   ? AR_HHF16
                                               : AR_F32;
   const bool refine = !fp64_only && o.refine != ZF_REFINE_OFF;
   const Arith hd = o.refine == ZF_REFINE_F32 ? AR_F32 : AR_F64;
@@ -604,7 +639,7 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   const bool high = refine && hd == AR_F64;  // FP64 master in the refinement phase
   const bool learned = !Z0 && o.z0 == 1;
   const bool need_pairs = ar_pairs(la) || (refine && ar_pairs(hc));
-  const bool need_f32 = la == AR_F32 || (refine && hd == AR_F32);
+  const bool need_f32 = la == AR_F32 || ar_f16(la) || (refine && hd == AR_F32);
   const bool use_h = fp64_only || high;
   const bool mixed = !fp64_only;  // FP32 master Z in the first phase
   const bool s_pairs = ar_pairs(la);
@@ -619,6 +654,8 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   c.order = o.order;
   c.st = st;
   c.keep_pairs = la == AR_F32 && refine && ar_pairs(hc);
+  c.sigma = 1.0;
+  const int s_fmt = ar_f16(la) ? 2 : 1;  // split format of S: FP16 or BF16 halves
   series(o.order, c.c);
   const int max_l = o.max_sweeps > 0 ? o.max_sweeps : 100;
   const int max_h = o.max_refine > 0 ? o.max_refine : 10;
@@ -626,11 +663,11 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   // setup: operands of S, then Z0
   HIP_TRY(launch_split_pad(S, n, n, np, s_pairs ? w->s_hi : nullptr, s_pairs ? w->s_lo : nullptr,
                            (use_h || learned) ? w->s64 : nullptr,
-                           need_f32 ? w->s32 : nullptr, false, 1, st));
+                           need_f32 ? w->s32 : nullptr, false, s_fmt, st));
   int z0_used = Z0 ? ZF_Z0_GIVEN : ZF_Z0_SCALED_IDENTITY;
   int guess_flags = 0;
   if (learned) {
-    int lr = learned_guess(c, S, mixed, fp64_only, s_pairs, st);
+    int lr = learned_guess(c, S, mixed, fp64_only, s_pairs, ar_pm(la), st);
     if (lr < 0) return lr;
     if (lr == 1) z0_used = ZF_Z0_LEARNED;
     else guess_flags |= ZF_WARN_Z0_FALLBACK;
@@ -651,6 +688,9 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
                                  st));
   }
   if (la == AR_F32) HIP_TRY(launch_widen(w->z32[0], np, nullptr, nullptr, st, w->zc32[0]));
+  if (ar_f16(la))  // the initializers write BF16 pairs; the FP16 halves replace them
+    HIP_TRY(launch_widen(w->z32[0], np, nullptr, nullptr, st, nullptr, w->zr_hi[0], w->zr_lo[0],
+                         w->zc_hi[0], w->zc_lo[0], 1.0f, PAIR_F16));
 
   std::vector<double> h;
   int cur = 0;
@@ -663,7 +703,13 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
     if (pl.capped) flags |= ZF_WARN_MAXSWEEPS;
     if (refine) {
       // Algorithm 3: Z into the refinement arithmetic, then its own ratio-stopped loop
-      if (high) HIP_TRY(launch_widen(w->z32[cur], np, w->z64r[cur], w->z64c[cur], st));
+      // (a BF16x3 correction after FP16 halves needs Z's BF16 pair too)
+      const bool bf16_pairs = ar_pairs(hc) && ar_f16(la);
+      if (high)
+        HIP_TRY(launch_widen(w->z32[cur], np, w->z64r[cur], w->z64c[cur], st, nullptr,
+                             bf16_pairs ? w->zr_hi[cur] : nullptr,
+                             bf16_pairs ? w->zr_lo[cur] : nullptr, nullptr, nullptr, 1.0f,
+                             PAIR_BF16));
       else if (la != AR_F32) HIP_TRY(launch_widen(w->z32[cur], np, nullptr, nullptr, st, w->zc32[cur]));
       rc = run_phase(c, hd, hc, high, o.stop, max_h, cur, h, ph);
       if (rc < 0) goto done;
@@ -905,8 +951,7 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
               void* stream) {
   if (!A || !B || !C || m <= 0 || nn <= 0 || k <= 0) return fail(ZF_ERR_ARG, "bad gemm arguments");
   if (sym && m != nn) return fail(ZF_ERR_ARG, "symmetric mode needs m == nn");
-  if (precision != ZF_FP64 && precision != ZF_BF16X3 && precision != ZF_BF16 &&
-      precision != ZF_FP32)
+  if (precision < ZF_FP64 || precision > ZF_FP16)
     return fail(ZF_ERR_ARG, "precision %d not supported", precision);
   hipStream_t st = (hipStream_t)stream;
   // pad every operand to a common square tile multiple
@@ -955,7 +1000,13 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
   if (sym) ep.ot64 = c64;
   ep.partials = part;
   u16 *ah = nullptr, *al = nullptr, *bh = nullptr, *bl = nullptr;
-  const bool pairs = precision == ZF_BF16X3 || precision == ZF_BF16;
+  const bool pairs = precision == ZF_BF16X3 || precision == ZF_BF16 ||
+                     precision == ZF_FP16X3 || precision == ZF_FP16;
+  const bool f16 = precision == ZF_FP16X3 || precision == ZF_FP16;
+  const int pm = precision == ZF_BF16 ? PM_HH
+                 : precision == ZF_FP16X3 ? PM_X3F16
+                 : precision == ZF_FP16   ? PM_HHF16
+                                          : PM_X3;
   if (he == hipSuccess && precision == ZF_FP32) {
     float *a32, *b32;
     if ((rc = alloc(e * 4, (void**)&a32)) || (rc = alloc(e * 4, (void**)&b32))) {
@@ -972,11 +1023,10 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
       cleanup();
       return rc;
     }
-    he = launch_split_flat(a64, (int64_t)e, ah, al, 1, st);
-    if (he == hipSuccess) he = launch_split_flat(b64, (int64_t)e, bh, bl, 1, st);
+    he = launch_split_flat(a64, (int64_t)e, ah, al, f16 ? 2 : 1, st);
+    if (he == hipSuccess) he = launch_split_flat(b64, (int64_t)e, bh, bl, f16 ? 2 : 1, st);
     if (he == hipSuccess)
-      he = launch_gemm_x3(ah, al, np, bh, bl, np, np, np, np, sym != 0, ep, st,
-                          precision == ZF_BF16);
+      he = launch_gemm_x3(ah, al, np, bh, bl, np, np, np, np, sym != 0, ep, st, pm);
   } else if (he == hipSuccess) {
     he = launch_gemm_f64(a64, np, b64, np, np, np, np, sym != 0, ep, st);
   }

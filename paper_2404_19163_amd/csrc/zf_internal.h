@@ -8,6 +8,13 @@ namespace zf {
 
 typedef uint16_t u16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// Product modes of the 16-bit-halves GEMM: bit 0 = hi halves only ((h)(h)),
+// bit 1 = FP16 halves (else BF16).
+enum { PM_X3 = 0, PM_HH = 1, PM_X3F16 = 2, PM_HHF16 = 3 };
+// Format of a 16-bit pair in memory (EpiParams::pair_fmt, element-wise kernels).
+enum { PAIR_BF16 = 0, PAIR_F16 = 1 };
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -41,6 +48,13 @@ __device__ __forceinline__ void split_bf16(float x, u16& hi, u16& lo) {
 __device__ __forceinline__ void split_f16(float x, u16& hi, u16& lo) {
   hi = f32_to_f16_rne(x);
   lo = f32_to_f16_rne(x - f16_to_f32(hi));
+}
+__device__ __forceinline__ void split_pair(float x, u16& hi, u16& lo, int fmt) {
+  if (fmt == PAIR_F16) split_f16(x, hi, lo);
+  else split_bf16(x, hi, lo);
+}
+__device__ __forceinline__ float pair_sum(u16 hi, u16 lo, int fmt) {
+  return fmt == PAIR_F16 ? f16_to_f32(hi) + f16_to_f32(lo) : bf16_to_f32(hi) + bf16_to_f32(lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -109,6 +123,7 @@ struct EpiParams {
   u16* othi;
   u16* otlo;
   double* partials;  // per-tile sum of out^2 (FP64), or nullptr
+  int pair_fmt;      // PAIR_BF16 / PAIR_F16: format of dhi/dlo and of every pair output
 };
 
 // Launchers (return hipSuccess or the launch error).  All dimensions must be
@@ -120,10 +135,10 @@ int f64_tile_edge(int M, int N, bool sym);
 int f64_blocks(int M, int N, bool sym);
 int max_blocks(int M, int N);            // upper bound of the above (smallest tile edge)
 
-// hh: the (h)(h) scheme (hi halves only)
+// pm: product mode PM_* (BF16 or FP16 halves; all three products or (h)(h) only)
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
-                          hipStream_t st, bool hh = false);
+                          hipStream_t st, int pm = PM_X3);
 int f32_tile_edge(int M, int N, bool sym);
 int f32_blocks(int M, int N, bool sym);
 hipError_t launch_gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int N, int K,
@@ -145,9 +160,12 @@ hipError_t launch_init_identity(const double* g, int n, int np, float* z32, doub
 hipError_t launch_init_given(const double* Z0, int n, int np, float* z32, double* z64r,
                              double* z64c, u16* zr_hi, u16* zr_lo, u16* zc_hi, u16* zc_lo,
                              hipStream_t st);
-// FP32 Z -> FP64 row-major / FP64 transposed / FP32 transposed (each optional); np % 64 == 0
+// FP32 X -> FP64 row-major / FP64 transposed / FP32 transposed / 16-bit pairs of
+// scale * X (row-major and transposed, format fmt); each optional; np % 64 == 0
 hipError_t launch_widen(const float* z32, int np, double* z64r, double* z64c, hipStream_t st,
-                        float* zc32 = nullptr);
+                        float* zc32 = nullptr, u16* prh = nullptr, u16* prl = nullptr,
+                        u16* pch = nullptr, u16* pcl = nullptr, float scale = 1.0f,
+                        int fmt = PAIR_BF16);
 hipError_t launch_unpad_f64(const double* src, int np, int n, double* dst, hipStream_t st);
 hipError_t launch_unpad_f32(const float* src, int np, int n, double* dst, hipStream_t st);
 hipError_t launch_norm_finalize(const double* partials, int count, double* out, hipStream_t st);

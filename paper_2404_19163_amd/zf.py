@@ -18,19 +18,21 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libzf.so")
 
 # enums of include/zf.h
-FP64, BF16X3, FP16X3, BF16, FP32 = 0, 1, 2, 3, 4
+FP64, BF16X3, FP16X3, BF16, FP32, FP16 = 0, 1, 2, 3, 4, 5
 STOP_RATIO, STOP_MONOTONE = 0, 1
 REFINE_OFF, REFINE_F64_DELTA, REFINE_F64_FULL, REFINE_F32 = 0, 1, 2, 3
 WARN_MAXSWEEPS, WARN_Z0_FALLBACK, WARN_HIST_TRUNC = 1, 2, 4
 Z0_GIVEN, Z0_SCALED_IDENTITY, Z0_LEARNED = 0, 1, 2
 ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NONFINITE, ERR_NOT_CONVERGED = -1, -2, -3, -4, -5
 
-_PREC = {"fp64": FP64, "bf16x3": BF16X3, "fp16x3": FP16X3, "bf16": BF16, "fp32": FP32}
+_PREC = {"fp64": FP64, "bf16x3": BF16X3, "fp16x3": FP16X3, "bf16": BF16, "fp32": FP32,
+         "fp16": FP16}
 _STOP = {"ratio": STOP_RATIO, "monotone": STOP_MONOTONE}
 _REFINE = {"off": REFINE_OFF, "f64_delta": REFINE_F64_DELTA, "f64_full": REFINE_F64_FULL,
            "f32": REFINE_F32}
 KERNEL_CLASSES = ("gemm_x3", "gemm_x3_sym", "gemm_f64", "gemm_f64_sym", "gemm_hh", "gemm_hh_sym",
-                  "gemm_f32", "gemm_f32_sym")
+                  "gemm_f32", "gemm_f32_sym", "gemm_x3f16", "gemm_x3f16_sym", "gemm_hhf16",
+                  "gemm_hhf16_sym")
 
 
 class ZFError(RuntimeError):

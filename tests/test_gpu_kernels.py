@@ -139,6 +139,48 @@ def test_gemm_fp32(zf, m, nn, k, tile, monkeypatch):
     assert np.all(np.abs(C.cpu().numpy() - ref) <= bound)
 
 
+@pytest.mark.parametrize("prec", ["fp16x3", "fp16"])
+@pytest.mark.parametrize("m,nn,k", SHAPES)
+def test_gemm_fp16_halves(zf, prec, m, nn, k):
+    """FP16 halves (the paper's Eq. splitStyle): each product of halves is exact in
+    FP32 (11 + 11 significant bits), so the bound is the FP32 accumulation bound of
+    the (h)(h)(+(h)(l)+(l)(h)) sum of the oracle's FP16 split."""
+    rng = np.random.default_rng(m * 13 + nn + 3 * k)
+    A = rng.standard_normal((m, k))
+    B = rng.standard_normal((nn, k))
+    C, _ = zf.t_gemm(prec, _cuda(A), _cuda(B))
+    C = C.cpu().numpy()
+    ah, al = O.split(A, "fp16")
+    bh, bl = O.split(B, "fp16")
+    if prec == "fp16x3":
+        ref = O.split_product(ah, al, bh.T, bl.T)
+        absx = (np.abs(ah) + np.abs(al)).astype(float) @ (np.abs(bh) + np.abs(bl)).astype(float).T
+        assert np.all(np.abs(C - ref) <= 3 * k * U32 * absx)
+        exact = A @ B.T
+        u = 2.0 ** -11
+        assert np.all(np.abs(C - exact) <= (3 * u * u + 3 * k * U32) * (np.abs(A) @ np.abs(B).T) * 1.01)
+    else:
+        ref = ah.astype(float) @ bh.astype(float).T
+        bound = 2 * k * U32 * (np.abs(ah).astype(float) @ np.abs(bh).astype(float).T)
+        assert np.all(np.abs(C - ref) <= bound)
+
+
+def test_fp16_matrix_cores_keep_subnormal_halves(zf):
+    """Operands whose lo halves are FP16 subnormals (2^-24 .. 2^-14): the product
+    keeps them (a flushed lo would leave an error of the lo's size, far above the
+    accumulation bound)."""
+    rng = np.random.default_rng(3)
+    A = rng.uniform(0.5, 1.0, (128, 128)) * 2.0 ** -8 * np.sign(rng.standard_normal((128, 128)))
+    B = rng.uniform(0.5, 1.0, (128, 128))
+    ah, al = O.split(A, "fp16")
+    assert np.mean(np.abs(al[al != 0]) < 2.0 ** -14) > 0.5   # mostly subnormal lo halves
+    bh, bl = O.split(B, "fp16")
+    C, _ = zf.t_gemm("fp16x3", _cuda(A), _cuda(B))
+    ref = O.split_product(ah, al, bh.T, bl.T)
+    absx = (np.abs(ah) + np.abs(al)).astype(float) @ (np.abs(bh) + np.abs(bl)).astype(float).T
+    assert np.all(np.abs(C.cpu().numpy() - ref) <= 3 * 128 * U32 * absx)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("n,k", [(128, 128), (300, 200), (1000, 256)])
 def test_gemm_symmetric_fp32_hh(zf, prec, n, k):

@@ -106,11 +106,50 @@ def test_fp32_learned_and_given_guesses(zf):
     assert r.z0_used == zf.Z0_GIVEN
 
 
+@pytest.mark.parametrize("n,seed", [(256, 0), (300, 2), (129, 3)])
+def test_fp16_halves_paths(zf, n, seed):
+    """The paper's own FP16 halves: (h)(h)+(h)(l)+(l)(h) alone reaches a far lower floor
+    than with BF16 halves (u^2 = 2^-22 instead of 2^-16); with the FP64 refinement it
+    meets the mixed bar; (h)(h) with FP16 halves sits between (h)(h) with BF16 and the
+    split schemes."""
+    S = _S(n, seed)
+    Sd = _cuda(S)
+    ref = O.refine(S, O.scaled_identity_guess(S), order=2)
+    r16 = zf.refine(Sd, None, precision="fp16x3", refine="off")
+    rb = zf.refine(Sd, None, precision="bf16x3", refine="off")
+    r16r = zf.refine(Sd, None, precision="fp16x3", refine="f64_delta")
+    rh16 = zf.refine(Sd, None, precision="fp16", refine="off")
+    rhb = zf.refine(Sd, None, precision="bf16", refine="off")
+    e16, eb, e16r, eh16, ehb = (O.residual_rms(S, r.Z.cpu().numpy()) for r in (r16, rb, r16r, rh16, rhb))
+    print(f"n={n}: fp16x3 {e16:.2e} bf16x3 {eb:.2e} fp16x3+refi {e16r:.2e} fp16 {eh16:.2e} "
+          f"bf16 {ehb:.2e}", flush=True)
+    assert all(r.status == 0 for r in (r16, rb, r16r, rh16, rhb))
+    assert e16 <= 1e-6 and e16 * 8 <= eb
+    assert _rel(r16.Z.cpu().numpy(), ref.Z) <= 1e-5
+    assert e16r <= 1e-6 and r16r.high_evals >= 1
+    assert eh16 * 4 <= ehb and eh16 > e16
+
+
+def test_fp16_learned_and_refinement_modes(zf):
+    S = _S(200, 8)
+    for ref in ("f64_full", "f32"):
+        r = zf.refine(_cuda(S), None, precision="fp16x3", refine=ref)
+        rms = O.residual_rms(S, r.Z.cpu().numpy())
+        assert r.status == 0 and rms <= (1e-10 if ref == "f64_full" else 1e-5), (ref, rms)
+    for order in (1, 3):
+        r = zf.refine(_cuda(S), None, precision="fp16x3", order=order)
+        assert O.residual_rms(S, r.Z.cpu().numpy()) <= 1e-6
+
+
 def test_unknown_modes_rejected(zf):
     S = _cuda(_S(64, 0))
-    with pytest.raises(zf.ZFError):
-        zf.refine(S, None, precision="fp16x3")
     import ctypes
+    o = zf.Opts(2, 9, zf.STOP_RATIO, 100, 1, 10, 0)          # precision 9 does not exist
+    res = zf.Result()
+    Z = torch.empty_like(S)
+    rc = zf.lib().zf_refine_ex(S.data_ptr(), None, 64, ctypes.byref(o), Z.data_ptr(),
+                               ctypes.byref(res), None, 0, None)
+    assert rc == zf.ERR_ARG
     o = zf.Opts(2, zf.FP32, zf.STOP_RATIO, 100, 7, 10, 0)   # refine mode 7 does not exist
     res = zf.Result()
     Z = torch.empty_like(S)
