@@ -221,6 +221,15 @@ def residual_rms(S: np.ndarray, Z: np.ndarray) -> float:
     return residual(S, Z) / math.sqrt(S.shape[0])
 
 
+def congruence(H: np.ndarray, Z: np.ndarray) -> np.ndarray:
+    """H_perp = Z^T H Z (Sec. II.A, Eq. standard_form): with Z^T S Z = I the generalized
+    problem H C = S C eps becomes H_perp C_perp = C_perp eps, C_perp = Z^(-1) C.
+    Evaluated as Z^T (H Z), the order the two-product GPU path also takes."""
+    H = np.asarray(H, dtype=np.float64)
+    Z = np.asarray(Z, dtype=np.float64)
+    return Z.T @ (H @ Z)
+
+
 # ---------------------------------------------------------------------------
 # closed forms
 # ---------------------------------------------------------------------------

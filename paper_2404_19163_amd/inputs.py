@@ -25,6 +25,9 @@ Workload families (all FP64, row-major, symmetric, unit diagonal):
   warm-start workloads (the MD use case named in Sec. VI).
 * ``batched_overlaps`` -- many Gaussian-kernel matrices of uneven N with a
   controlled condition number.
+* ``huckel_hamiltonian`` -- a symmetric Hamiltonian matching an overlap S
+  (extended-Hueckel form), the H of the generalized problem H C = S C eps that
+  Z^T S Z = I reduces to standard form (Sec. II.A).
 """
 from __future__ import annotations
 
@@ -207,6 +210,16 @@ def paper_synthetic(n: int, gamma: float = 0.5) -> np.ndarray:
 def uniform_noise(n: int, seed: int) -> np.ndarray:
     """U_ij ~ U(-0.5, 0.5), seeded (the perturbation of Sec. V.A)."""
     return np.random.default_rng(seed).uniform(-0.5, 0.5, size=(n, n))
+
+
+def huckel_hamiltonian(S: np.ndarray, seed: int, k: float = 1.75, e_lo: float = -14.0,
+                       e_hi: float = -6.0) -> np.ndarray:
+    """H_ii = e_i with on-site energies e_i ~ U(e_lo, e_hi) (eV), H_ij = k S_ij (e_i + e_j)/2
+    (Wolfsberg-Helmholz).  Symmetric, indefinite in general."""
+    e = np.random.default_rng(seed).uniform(e_lo, e_hi, size=S.shape[0])
+    H = k * S * (0.5 * (e[:, None] + e[None, :]))
+    np.fill_diagonal(H, e)
+    return 0.5 * (H + H.T)
 
 
 # --------------------------------------------------------------------------

@@ -7,6 +7,7 @@ import pytest
 
 from oracle import zf_oracle as O
 from tests import test_oracle_coeffs as TC
+from tests import test_oracle_congruence as TH
 from tests import test_oracle_recursion as TR
 from tests import test_oracle_split as TS
 
@@ -29,6 +30,10 @@ def _transposed_gram(S, Z):
     return Z @ S @ Z.T
 
 
+def _mirrored_congruence(H, Z):
+    return Z @ H @ Z.T
+
+
 def _truncating_split(a, fmt="bf16"):
     a32 = O.to_fp32(a)
     u = np.ascontiguousarray(a32).view(np.uint32) & np.uint32(0xFFFF0000)
@@ -49,6 +54,8 @@ MUTANTS = [
     ("delta_coefficients", _dropped_term, lambda g: TC.test_x_form_coefficients_match_appendix_a(g)),
     ("correction", _flipped_correction, lambda g: TR.test_spectral_map_history()),
     ("gram", _transposed_gram, lambda g: TR.test_general_guess_limit()),
+    ("congruence", _mirrored_congruence, lambda g: TH.test_back_transform_solves_generalized_problem()),
+    ("congruence", _mirrored_congruence, lambda g: TH.test_exact_rational()),
     ("split", _truncating_split, lambda g: TS.test_bf16_rounding_edge_values()),
     ("stop_now", _nonstrict_stop, lambda g: TC.test_stop_rule_algorithm_2()),
 ]
