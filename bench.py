@@ -95,7 +95,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gauss4096",
-                    choices=sorted(WORKLOADS) + ["batched512", "md3000", "table1"])
+                    choices=sorted(WORKLOADS) + ["batched512", "md3000", "table1", "congruence"])
     ap.add_argument("--n", type=int, default=4096, help="order of the table1 workload")
     ap.add_argument("--frames", type=int, default=64, help="frames of the md3000 workload")
     ap.add_argument("--seed", type=int, default=0)
@@ -131,6 +131,8 @@ def main() -> int:
         return bench_md(args)
     if args.workload == "table1":
         return bench_table1(args)
+    if args.workload == "congruence":
+        return bench_congruence(args)
     wl = WORKLOADS[args.workload]
     n = wl["n"]
     t0 = time.perf_counter()
@@ -331,6 +333,59 @@ def bench_table1(args) -> int:
             "config": {"workload": f"Sec. V.A synthetic S (gamma 0.5), N={n}, Z0 = S^-1/2 + 0.005 U",
                        "seed": args.seed},
             "schemes": rows}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_congruence(args) -> int:
+    """The consumer of Z (Sec. II.A, Eq. standard_form): H_perp = Z^T H Z for the N = 4096
+    Gaussian-kernel overlap and its extended-Hueckel Hamiltonian, Z from the mixed
+    refinement.  Per precision: time per transform, algorithmic TFLOP/s (4 N^3: two dense
+    products), the largest deviation of H_perp's spectrum from that of the FP64 transform,
+    and relative Frobenius error.  torch's FP64 Z^T (H Z) (the vendor BLAS) is timed as
+    context."""
+    import numpy as np
+    import torch
+
+    from paper_2404_19163_amd import inputs, zf
+
+    S_np = inputs.workload("gauss4096", args.seed)
+    H_np = inputs.huckel_hamiltonian(S_np, 100 + args.seed)
+    n = S_np.shape[0]
+    S = torch.from_numpy(S_np).to("cuda:0")
+    H = torch.from_numpy(H_np).to("cuda:0")
+    Z = zf.refine(S, None, precision="bf16x3").Z
+    out = torch.empty_like(S)
+    ref = zf.congruence(H, Z, precision="fp64")
+    w_ref = torch.linalg.eigvalsh(ref)
+    flops = 4.0 * n ** 3
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps * 1e3
+
+    rows = {}
+    for prec in ("fp64", "bf16x3", "fp16x3", "fp32", "bf16", "fp16"):
+        ms = timed(lambda: zf.congruence(H, Z, precision=prec, out=out))
+        w = torch.linalg.eigvalsh(out)
+        rows[prec] = {"ms": round(ms, 3), "alg_tflops": round(flops / ms / 1e9, 1),
+                      "eig_dev": float((w - w_ref).abs().max()),
+                      "rel_fro": float(torch.linalg.norm(out - ref) / torch.linalg.norm(ref))}
+        print(f"[bench] congruence {prec}: {ms:.3f} ms", file=sys.stderr, flush=True)
+    ms = timed(lambda: Z.T @ (H @ Z))
+    rows["torch fp64 (vendor BLAS)"] = {"ms": round(ms, 3), "alg_tflops": round(flops / ms / 1e9, 1)}
+    line = {"metric": "congruence transform Z^T H Z: time per transform", "unit": "ms",
+            "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "data": "synthetic", "config": {"workload": "gauss4096 overlap + extended-Hueckel H, "
+                                                        "N=4096, Z from the mixed refinement",
+                                            "seed": args.seed},
+            "max_abs_eig": float(w_ref.abs().max()), "precisions": rows}
     print(json.dumps(line), flush=True)
     return 0
 

@@ -220,6 +220,24 @@ int zf_mlp_grad(const float* feats, const float* labels, int batch, float* grad_
 /* raw coefficients (host, 3 doubles) predicted for one device feature vector */
 int zf_mlp_predict(const float* feats, double* coef_host, void* stream);
 
+/* zf_congruence -- Hp = Z^T H Z, the congruence transform that turns the generalized
+ * eigenproblem H C = S C eps into the standard one Hp C' = C' eps once Z^T S Z = I
+ * (Sec. II.A, Eq. standard_form, with C' = Z^{-1} C).
+ *   H:  device, n x n FP64, row-major, symmetric (only its symmetry is assumed: the
+ *       first product reads H's rows as its columns).
+ *   Z:  device, n x n FP64, row-major (typically the Z returned by zf_refine).
+ *   Hp: device, n x n FP64, row-major, written in full and exactly symmetric (the upper
+ *       triangle is computed and mirrored).  Hp may alias H or Z: both are copied into
+ *       the library's workspace before anything is written.
+ *   precision: the arithmetic of both products, as for zf_refine's first phase:
+ *       ZF_FP64 (FP64 matrix cores), ZF_BF16X3 / ZF_FP16X3 (split halves, three
+ *       products, FP32 accumulation), ZF_BF16 / ZF_FP16 ((h)(h) only), ZF_FP32.  With
+ *       FP16 halves the entries of H, Z and Z^T H must stay below 65504 in magnitude.
+ *   Stream-ordered; does not synchronize.  Errors: ZF_ERR_ARG (NULL pointer, n < 1 or
+ *   n > 46000, unknown precision), ZF_ERR_NOMEM, ZF_ERR_HIP; on error Hp is undefined. */
+int zf_congruence(const double* H, const double* Z, int n, int precision, double* Hp,
+                  void* stream);
+
 /* zf_residual -- err_f = ||Z^T S Z - I||_F evaluated with FP64 products (host double).
  * S, Z: device n x n FP64. */
 int zf_residual(const double* S, const double* Z, int n, double* err_f, void* stream);

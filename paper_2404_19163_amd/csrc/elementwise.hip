@@ -142,33 +142,58 @@ hipError_t launch_init_identity(const double* g, int n, int np, float* z32, doub
   return hipGetLastError();
 }
 
-// Given Z0 (n x n, ld n): padded copies in row-major and transposed layouts.
-__global__ void init_given_kernel(const double* __restrict__ Z0, int n, int np, float* z32,
-                                  double* z64r, double* z64c, u16* zr_hi, u16* zr_lo, u16* zc_hi,
-                                  u16* zc_lo) {
-  const size_t total = (size_t)np * np;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e / np), j = (int)(e % np);
+// Given Z0 (n x n, ld n): padded copies in row-major and transposed layouts.  One
+// 64 x 64 tile per block; the transposed copies go through a padded LDS tile so that
+// Z0 is read, and every layout written, in contiguous rows.  The pairs are the split
+// of Z0's FP32 value.
+__global__ void __launch_bounds__(256) init_given_kernel(const double* __restrict__ Z0, int n,
+                                                         int np, float* __restrict__ z32,
+                                                         double* __restrict__ z64r,
+                                                         double* __restrict__ z64c,
+                                                         u16* __restrict__ zr_hi,
+                                                         u16* __restrict__ zr_lo,
+                                                         u16* __restrict__ zc_hi,
+                                                         u16* __restrict__ zc_lo) {
+  __shared__ double t[64][65];
+  const int T = np / 64;
+  const int i0 = (blockIdx.x / T) * 64, j0 = (blockIdx.x % T) * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63, i = i0 + r, j = j0 + c;
     const double v = (i < n && j < n) ? Z0[(size_t)i * n + j] : 0.0;
-    const float f = (float)v;
-    const size_t t = (size_t)j * np + i;
-    u16 h, l;
-    split_bf16(f, h, l);
-    if (z32) z32[e] = f;
-    if (z64r) z64r[e] = v;
-    if (z64c) z64c[t] = v;
-    if (zr_hi) { zr_hi[e] = h; zr_lo[e] = l; }
-    if (zc_hi) { zc_hi[t] = h; zc_lo[t] = l; }
+    const size_t idx = (size_t)i * np + j;
+    if (z32) z32[idx] = (float)v;
+    if (z64r) z64r[idx] = v;
+    if (zr_hi) {
+      u16 h, l;
+      split_bf16((float)v, h, l);
+      zr_hi[idx] = h;
+      zr_lo[idx] = l;
+    }
+    t[r][c] = v;
+  }
+  if (!z64c && !zc_hi) return;
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;  // transposed row j0 + r, column i0 + c
+    const size_t idx = (size_t)(j0 + r) * np + i0 + c;
+    const double v = t[c][r];
+    if (z64c) z64c[idx] = v;
+    if (zc_hi) {
+      u16 h, l;
+      split_bf16((float)v, h, l);
+      zc_hi[idx] = h;
+      zc_lo[idx] = l;
+    }
   }
 }
 
 hipError_t launch_init_given(const double* Z0, int n, int np, float* z32, double* z64r,
                              double* z64c, u16* zr_hi, u16* zr_lo, u16* zc_hi, u16* zc_lo,
                              hipStream_t st) {
-  const size_t total = (size_t)np * np;
-  hipLaunchKernelGGL(init_given_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, Z0, n, np,
-                     z32, z64r, z64c, zr_hi, zr_lo, zc_hi, zc_lo);
+  if (np % 64 != 0 || n > np) return hipErrorInvalidValue;
+  const int T = np / 64;
+  hipLaunchKernelGGL(init_given_kernel, dim3(T * T), dim3(256), 0, st, Z0, n, np, z32, z64r, z64c,
+                     zr_hi, zr_lo, zc_hi, zc_lo);
   return hipGetLastError();
 }
 

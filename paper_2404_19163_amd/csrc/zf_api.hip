@@ -819,6 +819,73 @@ int zf_residual(const double* S, const double* Z, int n, double* err_f, void* st
   return 0;
 }
 
+// H_perp = Z^T H Z (Sec. II.A, Eq. standard_form) with the residual's two matrix-core
+// products: first A^T = Z^T H (H symmetric, so the NT kernel reads it row-major), then
+// the symmetric product Z^T A written in FP64.  Both inputs are staged into the
+// workspace before the first product, so Hp may alias H or Z.
+int zf_congruence(const double* H, const double* Z, int n, int precision, double* Hp,
+                  void* stream) {
+  if (!H || !Z || !Hp) return fail(ZF_ERR_ARG, "H, Z and Hp must be non-NULL device pointers");
+  if (n <= 0) return fail(ZF_ERR_ARG, "n must be >= 1 (got %d)", n);
+  if (n > 46000) return fail(ZF_ERR_ARG, "n = %d exceeds the supported maximum 46000", n);
+  if (precision < ZF_FP64 || precision > ZF_FP16)
+    return fail(ZF_ERR_ARG, "precision %d is not supported", precision);
+  hipStream_t st = (hipStream_t)stream;
+  const Arith ar = precision == ZF_FP64     ? AR_F64
+                   : precision == ZF_BF16X3 ? AR_X3
+                   : precision == ZF_BF16   ? AR_HH
+                   : precision == ZF_FP16X3 ? AR_X3F16
+                   : precision == ZF_FP16   ? AR_HHF16
+                                            : AR_F32;
+  const bool pairs = ar_pairs(ar);
+  const bool f16 = ar_f16(ar);
+  const int np = pad_order(n);
+  Workspace* w = nullptr;
+  ZF_TRY(ws_get(np, pairs, true, &w, ar == AR_F32 || f16));
+  EpiParams e1 = epi0(np, n), e2 = epi0(np, n);
+  e2.o64 = e2.ot64 = w->d64;
+  int rc = 0;
+  if (pairs) {
+    HIP_TRY(launch_split_pad(H, n, n, np, w->s_hi, w->s_lo, nullptr, nullptr, false, f16 ? 2 : 1,
+                             st));
+    if (f16) {  // Z through its FP32 copy into FP16 halves (transposed layout)
+      HIP_TRY(launch_init_given(Z, n, np, w->z32[0], nullptr, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, st));
+      HIP_TRY(launch_widen(w->z32[0], np, nullptr, nullptr, st, nullptr, nullptr, nullptr,
+                           w->zc_hi[0], w->zc_lo[0], 1.0f, PAIR_F16));
+    } else {
+      HIP_TRY(launch_init_given(Z, n, np, nullptr, nullptr, nullptr, nullptr, nullptr, w->zc_hi[0],
+                                w->zc_lo[0], st));
+    }
+    e1.ohi = w->at_hi;
+    e1.olo = w->at_lo;
+    e1.pair_fmt = f16 ? PAIR_F16 : PAIR_BF16;
+    e2.pair_fmt = e1.pair_fmt;
+    rc = gemm_x3(w->zc_hi[0], w->zc_lo[0], w->s_hi, w->s_lo, np, false, e1, st, ar_pm(ar));
+    if (!rc) rc = gemm_x3(w->zc_hi[0], w->zc_lo[0], w->at_hi, w->at_lo, np, true, e2, st, ar_pm(ar));
+  } else if (ar == AR_F32) {
+    HIP_TRY(launch_split_pad(H, n, n, np, nullptr, nullptr, nullptr, w->s32, false, 1, st));
+    HIP_TRY(launch_init_given(Z, n, np, w->z32[0], nullptr, nullptr, nullptr, nullptr, nullptr,
+                              nullptr, st));
+    HIP_TRY(launch_widen(w->z32[0], np, nullptr, nullptr, st, w->zc32[0]));
+    e1.o32 = w->a32t;
+    rc = gemm_f32(w->zc32[0], w->s32, np, false, e1, st);
+    if (!rc) rc = gemm_f32(w->zc32[0], w->a32t, np, true, e2, st);
+  } else {
+    HIP_TRY(launch_split_pad(H, n, n, np, nullptr, nullptr, w->s64, nullptr, false, 1, st));
+    HIP_TRY(launch_init_given(Z, n, np, nullptr, nullptr, w->z64c[0], nullptr, nullptr, nullptr,
+                              nullptr, st));
+    e1.o64 = w->a64t;
+    rc = gemm_f64(w->z64c[0], w->s64, np, false, e1, st);
+    if (!rc) rc = gemm_f64(w->z64c[0], w->a64t, np, true, e2, st);
+  }
+  if (rc) return rc;
+  HIP_TRY(launch_unpad_f64(w->d64, np, n, Hp, st));
+  if (g_prof.on) prof_harvest();
+  g_err.clear();
+  return 0;
+}
+
 void zf_release(void) {
   batch_release_all();
   if (g_ws.device >= 0) ws_free(g_ws);

@@ -61,7 +61,7 @@ EXPORTS = ("zf_default_opts", "zf_refine", "zf_refine_ex", "zf_residual", "zf_re
            "zf_batched_set_tiles", "zf_batched_get_tiles", "zf_batched_autotune",
            "zf_batched_use_graph", "zf_batched_release", "zf_features", "zf_guess_label",
            "zf_mlp_set_params", "zf_mlp_get_params", "zf_mlp_set_norm", "zf_mlp_train_step",
-           "zf_mlp_grad", "zf_mlp_predict", "zf_mlp_save", "zf_mlp_load")
+           "zf_mlp_grad", "zf_mlp_predict", "zf_mlp_save", "zf_mlp_load", "zf_congruence")
 N_PARAMS = 4931
 
 _lib = None
@@ -85,6 +85,8 @@ def lib() -> ctypes.CDLL:
     L.zf_refine_ex.restype = i
     L.zf_residual.argtypes = [vp, vp, i, P(d), vp]
     L.zf_residual.restype = i
+    L.zf_congruence.argtypes = [vp, vp, i, i, vp, vp]
+    L.zf_congruence.restype = i
     L.zf_release.argtypes = []
     L.zf_release.restype = None
     L.zf_last_error.argtypes = []
@@ -294,6 +296,19 @@ def residual(S: torch.Tensor, Z: torch.Tensor, stream=None) -> float:
     v = ctypes.c_double(0.0)
     _check(lib().zf_residual(_dev(S, "S", n), _dev(Z, "Z", n), n, ctypes.byref(v), _stream(stream)))
     return v.value
+
+
+def congruence(H: torch.Tensor, Z: torch.Tensor, *, precision: str = "fp64",
+               out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """H_perp = Z^T H Z (zf_congruence): the standard-form Hamiltonian once Z^T S Z = I.
+    `out` may be H or Z itself."""
+    n = H.shape[0]
+    h_ptr, z_ptr = _dev(H, "H", n), _dev(Z, "Z", n)
+    if out is None:
+        out = torch.empty_like(H)
+    _check(lib().zf_congruence(h_ptr, z_ptr, n, _PREC[precision], _dev(out, "out", n),
+                               _stream(stream)))
+    return out
 
 
 def release() -> None:
