@@ -231,6 +231,58 @@ def congruence(H: np.ndarray, Z: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# FP64 products emulated with integer slices (the multi-word splitting line that
+# Sec. I and Sec. III.A cite, carried to integer matrix cores): the Ozaki scheme
+# (Ozaki, Ogita, Oishi & Rump 2012) with 7-bit signed slices as in Ootomo, Ozaki &
+# Yokota 2024.  Used for the residual of the refinement phase (Sec. IV.B).
+# ---------------------------------------------------------------------------
+
+
+def int_slices(A: np.ndarray, s: int) -> tuple[list[np.ndarray], np.ndarray]:
+    """Row i of A as 2^{e_i} sum_{p=1..s} a_p 2^{-7p} plus a remainder below
+    2^{e_i - 7s}: e_i is the frexp exponent of max_k |A_ik| (0 for a zero row), so
+    |A_ik 2^{-e_i}| < 1; each slice takes the integer part of 128 times what is left
+    (truncation toward zero, |a_p| <= 127).  Every step is exact in FP64."""
+    A = np.asarray(A, dtype=np.float64)
+    m = np.max(np.abs(A), axis=1) if A.shape[1] else np.zeros(A.shape[0])
+    e = np.where(m > 0, np.frexp(m)[1], 0).astype(np.int64)
+    t = np.ldexp(A, -e[:, None])
+    out = []
+    for _ in range(s):
+        t = t * 128.0
+        q = np.trunc(t)
+        t = t - q
+        out.append(q.astype(np.int64))
+    return out, e
+
+
+def ozaki_product(A: np.ndarray, B: np.ndarray, s: int) -> np.ndarray:
+    """C = A B^T (A: M x K, B: N x K) from s slices per operand row, keeping the slice
+    products a_p b_q^T with p + q <= s + 1.  Products of one weight 2^{-7d}, d = p + q,
+    are summed exactly in integers; the weights are combined in FP64 from the smallest
+    (d = s + 1) to the largest (d = 2), then scaled by 2^{e_i + f_j}.
+    Error: |C - A B^T|_ij < (s + 1) 2^{-7s} K 2^{e_i + f_j}."""
+    sa, ea = int_slices(A, s)
+    sb, eb = int_slices(B, s)
+    acc = np.zeros((np.asarray(A).shape[0], np.asarray(B).shape[0]))
+    for d in range(s + 1, 1, -1):
+        c = sum(sa[p - 1] @ sb[d - p - 1].T for p in range(1, d))
+        acc = acc + np.ldexp(c.astype(np.float64), -7 * d)
+    return np.ldexp(acc, ea[:, None] + eb[None, :])
+
+
+def emulated_residual(S: np.ndarray, Z: np.ndarray, s: int) -> np.ndarray:
+    """delta = I - Z^T S Z with both products emulated (Sec. III.B order: A^T = Z^T S,
+    then Z^T A), the second one taken from its upper triangle and mirrored."""
+    S = np.asarray(S, dtype=np.float64)
+    Zt = np.ascontiguousarray(np.asarray(Z, dtype=np.float64).T)
+    At = ozaki_product(Zt, S, s)             # rows of Z^T against rows of S (= columns)
+    X = ozaki_product(Zt, At, s)             # (Z^T S Z)_ij = sum_k Z^T_ik At_jk
+    X = np.triu(X) + np.triu(X, 1).T
+    return np.eye(S.shape[0]) - X
+
+
+# ---------------------------------------------------------------------------
 # closed forms
 # ---------------------------------------------------------------------------
 

@@ -8,6 +8,7 @@ import pytest
 from oracle import zf_oracle as O
 from tests import test_oracle_coeffs as TC
 from tests import test_oracle_congruence as TH
+from tests import test_oracle_ozaki as TZ
 from tests import test_oracle_recursion as TR
 from tests import test_oracle_split as TS
 
@@ -34,6 +35,24 @@ def _mirrored_congruence(H, Z):
     return Z @ H @ Z.T
 
 
+_true_ozaki = O.ozaki_product
+
+
+def _ozaki_dropped_weight(A, B, s):
+    """Leaves out the products of weight 2^{-7(s+1)} (the p + q = s + 1 diagonal)."""
+    sa, ea = O.int_slices(A, s)
+    sb, eb = O.int_slices(B, s)
+    acc = np.zeros((A.shape[0], B.shape[0]))
+    for d in range(s, 1, -1):
+        c = sum(sa[p - 1] @ sb[d - p - 1].T for p in range(1, d))
+        acc = acc + np.ldexp(c.astype(np.float64), -7 * d)
+    return np.ldexp(acc, ea[:, None] + eb[None, :])
+
+
+def _ozaki_shifted(A, B, s):
+    return 2.0 * _true_ozaki(A, B, s)
+
+
 def _truncating_split(a, fmt="bf16"):
     a32 = O.to_fp32(a)
     u = np.ascontiguousarray(a32).view(np.uint32) & np.uint32(0xFFFF0000)
@@ -56,6 +75,8 @@ MUTANTS = [
     ("gram", _transposed_gram, lambda g: TR.test_general_guess_limit()),
     ("congruence", _mirrored_congruence, lambda g: TH.test_back_transform_solves_generalized_problem()),
     ("congruence", _mirrored_congruence, lambda g: TH.test_exact_rational()),
+    ("ozaki_product", _ozaki_dropped_weight, lambda g: TZ.test_product_within_bound_of_exact(3)),
+    ("ozaki_product", _ozaki_shifted, lambda g: TZ.test_integer_matrices_are_exact()),
     ("split", _truncating_split, lambda g: TS.test_bf16_rounding_edge_values()),
     ("stop_now", _nonstrict_stop, lambda g: TC.test_stop_rule_algorithm_2()),
 ]
