@@ -203,6 +203,26 @@ def main() -> int:
         print(f"[bench] fp64: {fp64_s * 1e3:.3f} ms/step iters={r64.iters} rms={r64.final_rms:.3e}",
               file=sys.stderr, flush=True)
 
+    # ---- mixed path with the emulated FP64 residual (int8 matrix cores) ----
+    emu = None
+    if not args.mixed_only and args.fp64_steps > 0 and n <= 16384:
+        Ze = torch.empty_like(S)
+        zf.refine(S, None, order=args.order, precision="bf16x3", out=Ze, stream=stream,
+                  refine="emu")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        re_ = None
+        for _ in range(args.fp64_steps):
+            re_ = zf.refine(S, None, order=args.order, precision="bf16x3", out=Ze, stream=stream,
+                            refine="emu")
+        torch.cuda.synchronize()
+        emu_s = (time.perf_counter() - t0) / args.fp64_steps
+        emu = {"ms": round(emu_s * 1e3, 3), "evals": [re_.low_evals, re_.high_evals],
+               "final_rms": re_.final_rms, "slices": int(os.environ.get("ZF_EMU_SLICES", "7")),
+               "fp64_rms": zf.residual(S, Ze) / math.sqrt(n)}
+        print(f"[bench] mixed, emulated FP64 residual: {emu_s * 1e3:.3f} ms/step "
+              f"rms={re_.final_rms:.3e}", file=sys.stderr, flush=True)
+
     # ---- residuals checked by the CPU oracle ----------------------------
     from oracle import zf_oracle as O
     Zm_np = Zm.cpu().numpy()
@@ -251,6 +271,7 @@ def main() -> int:
         "final_rms": last.final_rms,
         "fp64": fp64,
         "speedup_vs_fp64": round(fp64["ms"] / (mixed_s * 1e3), 3) if fp64 else None,
+        "mixed_emulated_residual": emu,
         "checks": checks,
         "kernels": kernels,
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(ach, 2), "peak": peak,

@@ -83,8 +83,14 @@ enum zf_refine_mode {
   ZF_REFINE_OFF = 0,       /* return the first phase's result                         */
   ZF_REFINE_F64_DELTA = 1, /* FP64 delta and stop norm, BF16x3 correction              */
   ZF_REFINE_F64_FULL = 2,  /* FP64 delta and FP64 correction                          */
-  ZF_REFINE_F32 = 3        /* FP32 delta, stop norm and correction (Algorithm 3 with
+  ZF_REFINE_F32 = 3,       /* FP32 delta, stop norm and correction (Algorithm 3 with
                               FP32[Z], the "+refi" of Table I in single precision)    */
+  ZF_REFINE_EMU = 4        /* delta and stop norm from FP64 products emulated on the
+                              int8 matrix cores (7-bit integer slices, Ozaki scheme;
+                              ZF_EMU_SLICES = 3..8 slices, default 7), BF16x3
+                              correction.  Each product's error is below
+                              (s+1) 2^-7s n 2^(e_i+f_j), e_i, f_j the exponents of the
+                              largest entries of the operand rows; n <= 16384.       */
 };
 
 typedef struct {
@@ -293,6 +299,20 @@ int zf_t_split(const double* a, int64_t count, uint16_t* hi, uint16_t* lo, int f
 int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, const double* B,
               double alpha, const double* D, double beta, double gamma, double* C,
               double* norm_sq, void* stream);
+
+/*
+ * zf_t_ozaki -- zf_t_gemm's product and epilogue with A B^T emulated from `slices`
+ * (1..8) 7-bit integer slices per operand row on the int8 matrix cores (the
+ * refinement residual's arithmetic under ZF_REFINE_EMU): row i of A is scaled by
+ * 2^-e_i (e_i the frexp exponent of its largest magnitude) and cut into slices
+ * a_p (|a_p| <= 127) by repeated truncation of 128 times the rest; the products
+ * a_p b_q^T with p + q <= slices + 1 are summed exactly in int32 per weight 2^-7(p+q)
+ * and the weights combined in FP64 from the smallest.  max(m, nn, k) <= 16384.
+ * A row holding a non-finite entry gives NaN products.
+ */
+int zf_t_ozaki(int slices, int sym, int m, int nn, int k, const double* A, const double* B,
+               double alpha, const double* D, double beta, double gamma, double* C,
+               double* norm_sq, void* stream);
 
 /* zf_t_gershgorin -- g = max_i sum_j |S_ij| (host double) for device S (n x n). */
 int zf_t_gershgorin(const double* S, int n, double* g, void* stream);

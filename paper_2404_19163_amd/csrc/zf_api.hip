@@ -70,11 +70,12 @@ static int pad_order(int n) { return n >= 1024 ? round_up(n, 256) : round_up(n, 
 // ---------------------------------------------------------------------------
 enum KClass {
   K_X3 = 0, K_X3_SYM, K_F64, K_F64_SYM, K_HH, K_HH_SYM, K_F32, K_F32_SYM, K_X3F16, K_X3F16_SYM,
-  K_HHF16, K_HHF16_SYM, K_COUNT
+  K_HHF16, K_HHF16_SYM, K_OZ, K_OZ_SYM, K_COUNT
 };
 static const char* kClassName[K_COUNT] = {
     "gemm_x3", "gemm_x3_sym", "gemm_f64", "gemm_f64_sym", "gemm_hh", "gemm_hh_sym",
-    "gemm_f32", "gemm_f32_sym", "gemm_x3f16", "gemm_x3f16_sym", "gemm_hhf16", "gemm_hhf16_sym"};
+    "gemm_f32", "gemm_f32_sym", "gemm_x3f16", "gemm_x3f16_sym", "gemm_hhf16", "gemm_hhf16_sym",
+    "gemm_oz", "gemm_oz_sym"};
 
 struct PendingEvent {
   hipEvent_t a, b;
@@ -139,6 +140,10 @@ struct Workspace {
   // FP64
   double *s64 = nullptr, *z64r[2] = {}, *z64c[2] = {}, *a64t = nullptr, *d64 = nullptr;
   double *q64 = nullptr, *u64 = nullptr;
+  // emulated FP64 (integer slices): planes of S, Z^T and A^T = Z^T S, row exponents
+  bool has_oz = false;
+  signed char *oz_s = nullptr, *oz_z = nullptr, *oz_a = nullptr;
+  int *oz_es = nullptr, *oz_ez = nullptr, *oz_ea = nullptr;
   // scalars
   double *partials = nullptr, *err_dev = nullptr, *rowsum = nullptr, *g_dev = nullptr;
   double *gscr = nullptr, *cg = nullptr;  // learned-guess scratch (8192) and coefficients (8)
@@ -174,15 +179,17 @@ static int ws_alloc(Workspace& w, T** out, size_t elems) {
   return 0;
 }
 
-static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out, bool need_f32 = false) {
+static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out, bool need_f32 = false,
+                  bool need_oz = false) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   Workspace& w = g_ws;
   if (w.device != dev || w.np < np || (need_x3 && !w.has_x3) || (need_f64 && !w.has_f64) ||
-      (need_f32 && !w.has_f32)) {
+      (need_f32 && !w.has_f32) || (need_oz && !w.has_oz)) {
     const bool keep_x3 = (w.device == dev) && w.has_x3;
     const bool keep_f64 = (w.device == dev) && w.has_f64;
     const bool keep_f32 = (w.device == dev) && w.has_f32;
+    const bool keep_oz = (w.device == dev) && w.has_oz;
     const int np_new = (w.device == dev && w.np > np) ? w.np : np;
     ws_free(w);
     w.device = dev;
@@ -192,6 +199,7 @@ static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out, bool nee
     w.has_x3 = need_x3 || keep_x3;
     w.has_f64 = need_f64 || keep_f64;
     w.has_f32 = need_f32 || keep_f32;
+    w.has_oz = need_oz || keep_oz;
     ZF_TRY(ws_alloc(w, &w.partials, tiles));
     ZF_TRY(ws_alloc(w, &w.err_dev, 8));
     ZF_TRY(ws_alloc(w, &w.rowsum, np_new));
@@ -241,6 +249,14 @@ static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out, bool nee
         ZF_TRY(ws_alloc(w, &w.z64r[b], m));
         ZF_TRY(ws_alloc(w, &w.z64c[b], m));
       }
+    }
+    if (w.has_oz) {
+      ZF_TRY(ws_alloc(w, &w.oz_s, m * kOzMaxSlices));
+      ZF_TRY(ws_alloc(w, &w.oz_z, m * kOzMaxSlices));
+      ZF_TRY(ws_alloc(w, &w.oz_a, m * kOzMaxSlices));
+      ZF_TRY(ws_alloc(w, &w.oz_es, np_new));
+      ZF_TRY(ws_alloc(w, &w.oz_ez, np_new));
+      ZF_TRY(ws_alloc(w, &w.oz_ea, np_new));
     }
   }
   *out = &w;
@@ -324,13 +340,36 @@ static int gemm_f64(const double* A, const double* B, int np, bool sym, const Ep
   return 0;
 }
 
+// Emulated FP64 product of two sliced matrices (s slices each).
+static int gemm_oz(const signed char* A, const int* ea, const signed char* B, const int* eb,
+                   int np, int s, bool sym, const EpiParams& ep, hipStream_t st) {
+  PendingEvent pe{};
+  const bool prof = g_prof.on;
+  if (prof) {
+    pe.a = take_event();
+    pe.b = take_event();
+    pe.cls = sym ? K_OZ_SYM : K_OZ;
+    // executed int8 matrix-core operations: s (s + 1) / 2 slice products per tile
+    const double t = (double)oz_tile_edge(np, sym);
+    pe.flops = 0.5 * s * (s + 1) * 2.0 * (double)oz_blocks(np, sym) * t * t * (double)np;
+    HIP_TRY(hipEventRecord(pe.a, st));
+  }
+  HIP_TRY(launch_gemm_oz(A, ea, B, eb, np, s, sym, ep, st));
+  if (prof) {
+    HIP_TRY(hipEventRecord(pe.b, st));
+    g_prof.pending.push_back(pe);
+  }
+  return 0;
+}
+
 // ---------------------------------------------------------------------------
 // the sweep
 // ---------------------------------------------------------------------------
 // Arithmetic of a sweep's residual evaluation or correction: BF16 pairs with the
 // (h)(h)+(h)(l)+(l)(h) scheme (X3) or the (h)(h) scheme (HH), FP32 ("single") or
 // FP64 matrix-core GEMMs (Table I).
-enum Arith { AR_X3 = 0, AR_HH, AR_F32, AR_F64, AR_X3F16, AR_HHF16 };
+// AR_EMU: FP64 residual emulated with integer slices on the int8 matrix cores.
+enum Arith { AR_X3 = 0, AR_HH, AR_F32, AR_F64, AR_X3F16, AR_HHF16, AR_EMU };
 
 static bool ar_pairs(Arith a) {
   return a == AR_X3 || a == AR_HH || a == AR_X3F16 || a == AR_HHF16;
@@ -347,6 +386,8 @@ struct Ctx {
   double c[8];      // c_k = C(2k,k)/4^k
   bool keep_pairs;  // FP32 updates also write the row-major BF16 pair (a later X3 correction)
   double sigma;     // power-of-two scale of the FP16 delta pairs (FP16 halves only)
+  int oz_slices = 7;     // slices per operand of the emulated residual
+  bool oz_s_ready = false;  // S's slices are in the workspace (once per call)
 };
 
 static void series(int m, double* c) {
@@ -396,6 +437,19 @@ static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
     }
     ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.at_hi, w.at_lo, np, true, e2, c.st, pm));
     blocks = x3_blocks(np, np, true);
+  } else if (da == AR_EMU) {  // A^T = Z^T S and Z^T A, both emulated, A^T kept in FP64
+    const int s = c.oz_slices;
+    if (!c.oz_s_ready) {
+      HIP_TRY(launch_oz_slice(w.s64, np, s, w.oz_s, w.oz_es, c.st));
+      c.oz_s_ready = true;
+    }
+    HIP_TRY(launch_oz_slice(w.z64c[cur], np, s, w.oz_z, w.oz_ez, c.st));
+    e1.o64 = w.a64t;
+    ZF_TRY(gemm_oz(w.oz_z, w.oz_ez, w.oz_s, w.oz_es, np, s, false, e1, c.st));
+    HIP_TRY(launch_oz_slice(w.a64t, np, s, w.oz_a, w.oz_ea, c.st));
+    e2.o64 = e2.ot64 = w.d64;
+    ZF_TRY(gemm_oz(w.oz_z, w.oz_ez, w.oz_a, w.oz_ea, np, s, true, e2, c.st));
+    blocks = oz_blocks(np, true);
   } else if (da == AR_F32) {
     e1.o32 = w.a32t;
     ZF_TRY(gemm_f32(w.zc32[cur], w.s32, np, false, e1, c.st));
@@ -440,7 +494,7 @@ static int build_q(Ctx& c, Arith da, Arith ca, QRef* q) {
     EpiParams e = epi0(np, c.n);
     e.alpha = c.c[k] * sg;
     e.beta = ((k == m - 1) ? c.c[m] : 1.0) / sg;
-    if (da == AR_F64) e.d64 = w.d64;
+    if (da == AR_F64 || da == AR_EMU) e.d64 = w.d64;
     else if (da == AR_F32 || f16) e.d32 = w.dl32;
     else {
       e.dhi = w.d_hi;
@@ -527,7 +581,8 @@ struct PhaseOut {
 // One phase of Algorithm 2: evaluate, stop test, update, ping-pong.
 static int run_phase(Ctx& c, Arith da, Arith ca, bool high, int stop_rule, int max_updates,
                      int& cur, std::vector<double>& hist, PhaseOut& out) {
-  static const char* kName[4] = {"BF16x3", "BF16", "FP32", "FP64"};
+  static const char* kName[7] = {"BF16x3", "BF16",   "FP32",         "FP64",
+                                 "FP16x3", "FP16", "emulated FP64"};
   double prev = 0.0;
   for (int it = 0;; ++it) {
     double err = 0.0;
@@ -608,6 +663,14 @@ static int learned_guess(Ctx& c, const double* S, bool mixed, bool use_h, bool p
   return 1;
 }
 
+// Slices per operand of the emulated residual: 7 (56 bits; the product's error is
+// below 8 2^-49 K 2^{e_i + f_j}); ZF_EMU_SLICES (3..8) overrides (tuning).
+static int oz_slices_env() {
+  const char* env = getenv("ZF_EMU_SLICES");
+  const int v = env ? atoi(env) : 7;
+  return (v >= 3 && v <= kOzMaxSlices) ? v : 7;
+}
+
 static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& o, double* Z,
                        zf_result* res, double* hist, int hist_cap, hipStream_t st) {
   if (!S || !Z) return fail(ZF_ERR_ARG, "S and Z must be non-NULL device pointers");
@@ -617,8 +680,10 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
     return fail(ZF_ERR_ARG, "precision %d is not supported", o.precision);
   if (o.stop != ZF_STOP_RATIO && o.stop != ZF_STOP_MONOTONE)
     return fail(ZF_ERR_ARG, "unknown stop rule %d", o.stop);
-  if (o.refine < ZF_REFINE_OFF || o.refine > ZF_REFINE_F32)
+  if (o.refine < ZF_REFINE_OFF || o.refine > ZF_REFINE_EMU)
     return fail(ZF_ERR_ARG, "unknown refine mode %d", o.refine);
+  if (o.refine == ZF_REFINE_EMU && o.precision != ZF_FP64 && pad_order(n) > kOzMaxOrder)
+    return fail(ZF_ERR_ARG, "the emulated FP64 residual supports n <= %d (got %d)", kOzMaxOrder, n);
   if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(ZF_ERR_ARG, "bad hist buffer");
   if (n > 46000) return fail(ZF_ERR_ARG, "n = %d exceeds the supported maximum 46000", n);
   if (o.z0 != 0 && o.z0 != 1) return fail(ZF_ERR_ARG, "unknown guess kind %d", o.z0);
@@ -634,9 +699,9 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
                    : o.precision == ZF_FP16   ? AR_HHF16
                                               : AR_F32;
   const bool refine = !fp64_only && o.refine != ZF_REFINE_OFF;
-  const Arith hd = o.refine == ZF_REFINE_F32 ? AR_F32 : AR_F64;
-  const Arith hc = o.refine == ZF_REFINE_F64_DELTA ? AR_X3 : hd;
-  const bool high = refine && hd == AR_F64;  // FP64 master in the refinement phase
+  const Arith hd = o.refine == ZF_REFINE_F32 ? AR_F32 : o.refine == ZF_REFINE_EMU ? AR_EMU : AR_F64;
+  const Arith hc = (o.refine == ZF_REFINE_F64_DELTA || o.refine == ZF_REFINE_EMU) ? AR_X3 : hd;
+  const bool high = refine && (hd == AR_F64 || hd == AR_EMU);  // FP64 master
   const bool learned = !Z0 && o.z0 == 1;
   const bool need_pairs = ar_pairs(la) || (refine && ar_pairs(hc));
   const bool need_f32 = la == AR_F32 || ar_f16(la) || (refine && hd == AR_F32);
@@ -645,7 +710,7 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   const bool s_pairs = ar_pairs(la);
   const int np = pad_order(n);
   Workspace* w = nullptr;
-  ZF_TRY(ws_get(np, need_pairs, use_h || learned, &w, need_f32));
+  ZF_TRY(ws_get(np, need_pairs, use_h || learned, &w, need_f32, refine && hd == AR_EMU));
 
   Ctx c;
   c.w = w;
@@ -655,6 +720,8 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   c.st = st;
   c.keep_pairs = la == AR_F32 && refine && ar_pairs(hc);
   c.sigma = 1.0;
+  c.oz_slices = oz_slices_env();
+  c.oz_s_ready = false;
   const int s_fmt = ar_f16(la) ? 2 : 1;  // split format of S: FP16 or BF16 halves
   series(o.order, c.c);
   const int max_l = o.max_sweeps > 0 ? o.max_sweeps : 100;
@@ -1013,18 +1080,23 @@ int zf_t_split(const double* a, int64_t count, uint16_t* hi, uint16_t* lo, int f
   return 0;
 }
 
-int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, const double* B,
-              double alpha, const double* D, double beta, double gamma, double* C, double* norm_sq,
-              void* stream) {
+// precision < 0: the emulated product with oz_slices slices (zf_t_ozaki)
+static int t_gemm_impl(int precision, int oz_slices, int sym, int m, int nn, int k,
+                       const double* A, const double* B, double alpha, const double* D,
+                       double beta, double gamma, double* C, double* norm_sq, void* stream) {
   if (!A || !B || !C || m <= 0 || nn <= 0 || k <= 0) return fail(ZF_ERR_ARG, "bad gemm arguments");
   if (sym && m != nn) return fail(ZF_ERR_ARG, "symmetric mode needs m == nn");
-  if (precision < ZF_FP64 || precision > ZF_FP16)
-    return fail(ZF_ERR_ARG, "precision %d not supported", precision);
+  const bool oz = precision < 0;
+  if (!oz && precision > ZF_FP16) return fail(ZF_ERR_ARG, "precision %d not supported", precision);
+  if (oz && (oz_slices < 1 || oz_slices > kOzMaxSlices))
+    return fail(ZF_ERR_ARG, "slices must be in 1..%d (got %d)", kOzMaxSlices, oz_slices);
   hipStream_t st = (hipStream_t)stream;
   // pad every operand to a common square tile multiple
   int np = m > nn ? m : nn;
   if (k > np) np = k;
   np = round_up(np, 256);
+  if (oz && np > kOzMaxOrder)
+    return fail(ZF_ERR_ARG, "emulated products support dimensions up to %d", kOzMaxOrder);
   const size_t e = (size_t)np * np;
   std::vector<void*> tmp;
   auto alloc = [&](size_t bytes, void** p) -> int {
@@ -1074,7 +1146,18 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
                  : precision == ZF_FP16X3 ? PM_X3F16
                  : precision == ZF_FP16   ? PM_HHF16
                                           : PM_X3;
-  if (he == hipSuccess && precision == ZF_FP32) {
+  if (he == hipSuccess && oz) {
+    signed char *as, *bs;
+    int *ea, *eb;
+    if ((rc = alloc(e * oz_slices, (void**)&as)) || (rc = alloc(e * oz_slices, (void**)&bs)) ||
+        (rc = alloc((size_t)np * 4, (void**)&ea)) || (rc = alloc((size_t)np * 4, (void**)&eb))) {
+      cleanup();
+      return rc;
+    }
+    he = launch_oz_slice(a64, np, oz_slices, as, ea, st);
+    if (he == hipSuccess) he = launch_oz_slice(b64, np, oz_slices, bs, eb, st);
+    if (he == hipSuccess) he = launch_gemm_oz(as, ea, bs, eb, np, oz_slices, sym != 0, ep, st);
+  } else if (he == hipSuccess && precision == ZF_FP32) {
     float *a32, *b32;
     if ((rc = alloc(e * 4, (void**)&a32)) || (rc = alloc(e * 4, (void**)&b32))) {
       cleanup();
@@ -1103,7 +1186,8 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
       cleanup();
       return rc;
     }
-    const int nb = pairs ? x3_blocks(np, np, sym != 0)
+    const int nb = oz      ? oz_blocks(np, sym != 0)
+                   : pairs ? x3_blocks(np, np, sym != 0)
                    : precision == ZF_FP32 ? f32_blocks(np, np, sym != 0)
                                           : f64_blocks(np, np, sym != 0);
     he = launch_norm_finalize(part, nb, nrm, st);
@@ -1118,6 +1202,19 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
   if (he != hipSuccess) return fail(ZF_ERR_HIP, "zf_t_gemm: %s", hipGetErrorString(he));
   if (norm_sq) *norm_sq = nv * nv;
   return 0;
+}
+
+int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, const double* B,
+              double alpha, const double* D, double beta, double gamma, double* C, double* norm_sq,
+              void* stream) {
+  if (precision < ZF_FP64) return fail(ZF_ERR_ARG, "precision %d not supported", precision);
+  return t_gemm_impl(precision, 0, sym, m, nn, k, A, B, alpha, D, beta, gamma, C, norm_sq, stream);
+}
+
+int zf_t_ozaki(int slices, int sym, int m, int nn, int k, const double* A, const double* B,
+               double alpha, const double* D, double beta, double gamma, double* C,
+               double* norm_sq, void* stream) {
+  return t_gemm_impl(-1, slices, sym, m, nn, k, A, B, alpha, D, beta, gamma, C, norm_sq, stream);
 }
 
 int zf_t_gershgorin(const double* S, int n, double* g, void* stream) {

@@ -12,11 +12,15 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // Product modes of the 16-bit-halves GEMM: bit 0 = hi halves only ((h)(h)),
 // bit 1 = FP16 halves (else BF16).
-enum { PM_X3 = 0, PM_HH = 1, PM_X3F16 = 2, PM_HHF16 = 3 };
+// PM_I8: one product of signed 8-bit slices (16 per 16-byte chunk) with exact int32
+// accumulation, the accumulator registers holding the int32 bits
+enum { PM_X3 = 0, PM_HH = 1, PM_X3F16 = 2, PM_HHF16 = 3, PM_I8 = 4 };
 // Format of a 16-bit pair in memory (EpiParams::pair_fmt, element-wise kernels).
 enum { PAIR_BF16 = 0, PAIR_F16 = 1 };
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
 // FP32 -> BF16 with round to nearest, ties to even (NaN kept quiet).
@@ -145,6 +149,20 @@ hipError_t launch_gemm_f32(const float* A, int lda, const float* B, int ldb, int
                            bool sym, const EpiParams& ep, hipStream_t st);
 hipError_t launch_gemm_f64(const double* A, int lda, const double* B, int ldb, int M, int N, int K,
                            bool sym, const EpiParams& ep, hipStream_t st);
+
+// FP64 products emulated with 7-bit integer slices on the int8 matrix cores
+// (ozaki.hip).  Slices of M (np x np FP64, row-major): s planes of np x np signed
+// bytes (plane stride np^2) and a per-row exponent.  The GEMM forms the NT product
+// A B^T of two sliced matrices (np % 128 == 0, np <= kOzMaxOrder) with the
+// EpiParams epilogue; its norm partials number oz_blocks(np, sym).
+constexpr int kOzMaxSlices = 8;
+constexpr int kOzMaxOrder = 16384;  // s K 127^2 < 2^31 for every s <= 8
+hipError_t launch_oz_slice(const double* M, int np, int s, signed char* out, int* ex,
+                           hipStream_t st);
+hipError_t launch_gemm_oz(const signed char* A, const int* ea, const signed char* B, const int* eb,
+                          int np, int s, bool sym, const EpiParams& ep, hipStream_t st);
+int oz_tile_edge(int np, bool sym);
+int oz_blocks(int np, bool sym);
 
 // Elementwise / reduction kernels (elementwise.hip)
 hipError_t launch_split_pad(const double* src, int n, int ld_src, int np, u16* hi, u16* lo,
