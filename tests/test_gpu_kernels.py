@@ -260,3 +260,54 @@ def test_gershgorin(zf, n):
     S = S + S.T
     g = zf.t_gershgorin(_cuda(S))
     assert g == pytest.approx(O.gershgorin_max_row_sum(S), rel=1e-14)
+
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16", "fp16x3"])
+@pytest.mark.parametrize("m,nn,k", [(3072, 3072, 3072), (3000, 2900, 3100)])
+def test_gemm_large_tile_grid(zf, m, nn, k, prec):
+    """256-wide tiles on grids of 144 and 169 tiles (fewer than the CUs), with the
+    alpha D + beta A B^T epilogue and a ragged edge."""
+    rng = np.random.default_rng(m + nn + k)
+    A = rng.standard_normal((m, k)) * np.exp(rng.uniform(-3, 3, (m, 1)))
+    B = rng.standard_normal((nn, k))
+    D = rng.standard_normal((m, nn))
+    C, _ = zf.t_gemm(prec, _cuda(A), _cuda(B), alpha=0.5, D=_cuda(D), beta=0.375)
+    C = C.cpu().numpy()
+    fmt = "fp16" if prec == "fp16x3" else "bf16"
+    ah, al = O.split(A, fmt)
+    bh, bl = O.split(B, fmt)
+    if prec == "bf16":
+        ref = ah.astype(float) @ bh.astype(float).T
+        absx = np.abs(ah).astype(float) @ np.abs(bh).astype(float).T
+        terms = 2
+    else:
+        ref = O.split_product(ah, al, bh.T, bl.T)
+        absx = (np.abs(ah) + np.abs(al)).astype(float) @ (np.abs(bh) + np.abs(bl)).astype(float).T
+        terms = 3
+    ref = 0.5 * D + 0.375 * ref
+    bound = 0.375 * terms * k * U32 * absx + 1e-15 * np.abs(D)
+    assert np.all(np.abs(C - ref) <= bound)
+
+
+@pytest.mark.parametrize("k", [512, 4096])
+def test_gemm_symmetric_delta_n4096(zf, k):
+    """The N = 4096 symmetric product (136 tiles of 256) with the symmetric delta
+    epilogue, exact mirroring and the norm partials."""
+    n = 4096
+    rng = np.random.default_rng(k)
+    A = rng.standard_normal((n, k)) / math.sqrt(k)
+    M = rng.standard_normal((k, k))
+    M = (M + M.T) / 2
+    B = A @ M
+    C, nsq = zf.t_gemm("bf16x3", _cuda(A), _cuda(B), sym=True, beta=-1.0, gamma=1.0)
+    C = C.cpu().numpy()
+    assert np.array_equal(C, C.T)
+    ah, al = O.split(A)
+    bh, bl = O.split(B)
+    ref = np.eye(n) - O.split_product(ah, al, bh.T, bl.T)
+    tol = 3 * k * U32 * ((np.abs(ah) + np.abs(al)).astype(float)
+                         @ (np.abs(bh) + np.abs(bl)).astype(float).T) + 4 * U32
+    up = np.triu(np.ones((n, n), dtype=bool))
+    assert np.all((np.abs(C - ref) <= tol)[up])
+    assert nsq == pytest.approx(math.fsum((C * C).ravel().tolist()), rel=1e-12)
