@@ -74,12 +74,16 @@ struct TileTask {
 // ---------------------------------------------------------------------------
 // grouped GEMMs
 // ---------------------------------------------------------------------------
-using X3_64 = X3Cfg<64, 64, 32, 2, 2>;
-using X3_128 = X3Cfg<128, 128, 32, 2, 2>;
+// BF16x3 tiles: 64- or 128-wide, 4 waves, 2-stage load ring, two blocks per CU (in
+// grouped launches this beat 8 waves with a 3-stage ring: 55.6 vs 60 ms for the
+// 512-matrix batch); one grouped launch per tile edge.  FP64 tiles: 64 or 128 wide,
+// 4 waves.
+template <int T>
+using X3G = X3Cfg<T, T, 32, 2, 2>;
 using F64_64 = F64Cfg<64, 64, 16, 2, 2>;
 using F64_128 = F64Cfg<128, 128, 16, 2, 2>;
-static_assert(X3_64::NT == 256 && X3_128::NT == 256 && F64_64::NT == 256 && F64_128::NT == 256,
-              "grouped kernels run every tile body with one 256-thread block");
+static_assert(F64_64::NT == 256 && F64_128::NT == 256,
+              "the grouped FP64 kernel runs both tile bodies with one 256-thread block");
 
 __device__ __forceinline__ bool op_applies(int op, const BMat& M) {
   const int phase = M.phase, action = M.action;
@@ -97,16 +101,33 @@ __device__ __forceinline__ bool op_applies(int op, const BMat& M) {
   }
 }
 
-__global__ void __launch_bounds__(256, 2)
-    grouped_x3_kernel(const TileTask* __restrict__ tasks, int ntasks, const BMat* __restrict__ mats,
-                      int op, double c1, double c2, double* partials) {
-  __shared__ __attribute__((aligned(16))) u16 lds[2 * X3_128::STAGE_ELEMS];
-  __shared__ double red[4];
-  for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+// Task tables are XCD-major: seg[0..16] bounds 16 runs of tasks, runs 0-7 with
+// 128-wide tiles and runs 8-15 with 64-wide ones, run 8 p + x for XCD x.  Blocks are
+// dispatched round-robin over the 8 XCDs (block b on XCD b % 8), so block b walks
+// run x = b % 8 of its tile edge with stride gridDim.x / 8: the tiles of one matrix
+// run together on one XCD and share its L2 (the grid is a multiple of 8).
+__device__ __forceinline__ void xcd_run(const int* seg, int part, int& t0, int& t1, int& step) {
+  const int x = blockIdx.x & 7;
+  t0 = seg[8 * part + x] + (int)(blockIdx.x >> 3);
+  t1 = seg[8 * part + x + 1];
+  step = gridDim.x >> 3;
+}
+
+template <int T>
+__global__ void __launch_bounds__(X3G<T>::NT, 2)
+    grouped_x3_kernel(const TileTask* __restrict__ tasks, const int* __restrict__ seg,
+                      const BMat* __restrict__ mats, int op, double c1, double c2,
+                      double* partials) {
+  using CF = X3G<T>;
+  __shared__ __attribute__((aligned(16))) u16 lds[2 * CF::STAGE_ELEMS];
+  __shared__ double red[CF::NT / 64];
+  int t0, t1, step;
+  xcd_run(seg, T == 128 ? 0 : 1, t0, t1, step);
+  for (int t = t0; t < t1; t += step) {
     const TileTask tk = tasks[t];
     const BMat& M = mats[tk.m];
     if (!op_applies(op, M)) continue;
-    const int np = M.np, T = M.tile;
+    const int np = M.np;
     EpiParams ep;
     memset(&ep, 0, sizeof ep);
     ep.beta = 1.0;
@@ -173,22 +194,21 @@ __global__ void __launch_bounds__(256, 2)
       const int tiles = np / T;
       pidx = tk.ti * tiles - tk.ti * (tk.ti - 1) / 2 + (tk.tj - tk.ti);
     }
-    if (T == 64)
-      x3_tile<64, 64, 32, 2, 2>(ah, al, np, bh, bl, np, np, tk.ti * 64, tk.tj * 64, mode, ep, pidx,
-                                lds, red);
-    else
-      x3_tile<128, 128, 32, 2, 2>(ah, al, np, bh, bl, np, np, tk.ti * 128, tk.tj * 128, mode, ep,
-                                  pidx, lds, red);
+    x3_tile<T, T, 32, 2, 2>(ah, al, np, bh, bl, np, np, tk.ti * T, tk.tj * T, mode, ep, pidx, lds,
+                            red);
     __syncthreads();
   }
 }
 
 __global__ void __launch_bounds__(256, 2)
-    grouped_f64_kernel(const TileTask* __restrict__ tasks, int ntasks, const BMat* __restrict__ mats,
-                       int op, double* partials) {
+    grouped_f64_kernel(const TileTask* __restrict__ tasks, const int* __restrict__ seg,
+                       const BMat* __restrict__ mats, int op, double* partials) {
   __shared__ double lds[2 * F64_128::STAGE];
   __shared__ double red[4];
-  for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+  for (int part = 0; part < 2; ++part) {
+  int t0, t1, step;
+  xcd_run(seg, part, t0, t1, step);
+  for (int t = t0; t < t1; t += step) {
     const TileTask tk = tasks[t];
     const BMat& M = mats[tk.m];
     if (!op_applies(op, M)) continue;
@@ -223,6 +243,7 @@ __global__ void __launch_bounds__(256, 2)
       f64_tile<128, 128, 16, 2, 2>(a, np, b, np, np, tk.ti * 128, tk.tj * 128, mode, ep, pidx, lds,
                                    red);
     __syncthreads();
+  }
   }
 }
 
@@ -333,24 +354,30 @@ __global__ void __launch_bounds__(256) b_split_kernel(const BMat* __restrict__ m
   }
 }
 
-// Per-matrix statistics, one block of 4 waves per matrix, one wave per row:
-// stats[4m..] = {g = max r_i, g_lo = min (S_ii - (r_i - |S_ii|)), mean r_i, tr S},
-// r_i = sum_j |S_ij|.  Matrices taking the learned guess also get the Frobenius
-// products ||S||^2, <S, S^2>, ||S^2||^2 (S^2 from stage S2, FP32 in z32[1]) and
-// their 8 features.  Fixed-order reductions: repeatable bit for bit.
-__global__ void __launch_bounds__(256) b_stats_kernel(const BMat* __restrict__ mats,
-                                                      const double* const* S, double* g,
-                                                      double* stats, float* feats) {
-  const int m = blockIdx.x;
+// Per-matrix statistics: stats[4m..] = {g = max r_i, g_lo = min (S_ii - (r_i - |S_ii|)),
+// mean r_i, tr S}, r_i = sum_j |S_ij|.  Matrices taking the learned guess also get
+// the Frobenius products ||S||^2, <S, S^2>, ||S^2||^2 (S^2 from stage S2, FP32 in
+// z32[1]) and their 8 features.  Pass 1: one block per chunk of kStatRows rows (one
+// wave per row), 7 partial values per chunk; pass 2: one thread per matrix folds its
+// chunks in order.  Fixed-order reductions: repeatable bit for bit.
+constexpr int kStatRows = 32;
+
+__global__ void __launch_bounds__(256) b_stats_rows_kernel(const BMat* __restrict__ mats,
+                                                           const double* const* S, int chunks,
+                                                           double* __restrict__ part) {
+  const int m = blockIdx.y, c = blockIdx.x;
   const BMat& M = mats[m];
   const int n = M.n, np = M.np;
+  const int r0 = c * kStatRows;
+  if (r0 >= n) return;
+  const int r1 = r0 + kStatRows < n ? r0 + kStatRows : n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double* Sm = S[m];
   const float* S2 = M.z32[1];
   const bool learn = M.learn != 0;
   __shared__ double red[4][7];
   double mx = 0.0, mn = 1e300, sm = 0.0, tr = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int i = wave; i < n; i += 4) {
+  for (int i = r0 + wave; i < r1; i += 4) {
     const double* row = Sm + (size_t)i * n;
     double r = 0.0;
     for (int j = lane; j < n; j += 64) {
@@ -391,18 +418,37 @@ __global__ void __launch_bounds__(256) b_stats_kernel(const BMat* __restrict__ m
       red[0][1] = fmin(red[0][1], red[w][1]);
       for (int k = 2; k < 7; ++k) red[0][k] += red[w][k];
     }
-    const double gg = red[0][0];
-    g[m] = gg;
-    stats[4 * m + 0] = gg;
-    stats[4 * m + 1] = red[0][1];
-    stats[4 * m + 2] = red[0][2] / n;
-    stats[4 * m + 3] = red[0][3];
-    float* f = feats + 8 * (size_t)m;
-    if (learn)
-      finish_features(gg, red[0][1], red[0][2] / n, red[0][3], red[0][4], red[0][5], red[0][6], n, f);
-    else
-      for (int k = 0; k < 8; ++k) f[k] = 0.f;
+    double* o = part + ((size_t)m * chunks + c) * 7;
+    for (int k = 0; k < 7; ++k) o[k] = red[0][k];
   }
+}
+
+__global__ void b_stats_final_kernel(const BMat* __restrict__ mats, int count, int chunks,
+                                     const double* __restrict__ part, double* g, double* stats,
+                                     float* feats) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= count) return;
+  const BMat& M = mats[m];
+  const int n = M.n;
+  const int used = (n + kStatRows - 1) / kStatRows;
+  const double* p = part + (size_t)m * chunks * 7;
+  double v[7] = {p[0], p[1], p[2], p[3], p[4], p[5], p[6]};
+  for (int c = 1; c < used; ++c) {
+    const double* q = p + 7 * c;
+    v[0] = fmax(v[0], q[0]);
+    v[1] = fmin(v[1], q[1]);
+    for (int k = 2; k < 7; ++k) v[k] += q[k];
+  }
+  g[m] = v[0];
+  stats[4 * m + 0] = v[0];
+  stats[4 * m + 1] = v[1];
+  stats[4 * m + 2] = v[2] / n;
+  stats[4 * m + 3] = v[3];
+  float* f = feats + 8 * (size_t)m;
+  if (M.learn)
+    finish_features(v[0], v[1], v[2] / n, v[3], v[4], v[5], v[6], n, f);
+  else
+    for (int k = 0; k < 8; ++k) f[k] = 0.f;
 }
 
 // Acceptance of the predicted coefficients (one thread per matrix); on success
@@ -581,12 +627,48 @@ static int grow(void** p, size_t* cap, size_t need) {
 struct Plan {
   std::vector<BMat> mats;
   std::vector<TileTask> full, sym;
+  int fseg[17] = {}, sseg[17] = {};  // XCD-major run bounds of the two tables
   long long partials = 0;
   int max_etiles = 1;  // largest (np / 64)^2 of the batch: x extent of element-wise grids
   size_t arena = 0;
 };
 
-// Buffer sizes for every matrix, task tables sorted by order (largest first).
+// XCD-major task tables (see xcd_run): per tile edge, matrices go to the 8 XCDs in
+// snake order of decreasing order n (each XCD gets a like mix of sizes); within a run,
+// matrices by decreasing n, each matrix's tiles consecutive.
+static void build_tables(const std::vector<BMat>& mats, std::vector<TileTask>& full,
+                         std::vector<TileTask>& sym, int* fseg, int* sseg) {
+  full.clear();
+  sym.clear();
+  for (int part = 0; part < 2; ++part) {
+    const int edge = part == 0 ? 128 : 64;
+    std::vector<int> ms;
+    for (int m = 0; m < (int)mats.size(); ++m)
+      if (mats[m].tile == edge) ms.push_back(m);
+    std::stable_sort(ms.begin(), ms.end(), [&](int a, int b) { return mats[a].np > mats[b].np; });
+    std::vector<int> run[8];
+    for (int i = 0; i < (int)ms.size(); ++i) {
+      const int r = i / 8, pos = i % 8;
+      run[(r % 2 == 0) ? pos : 7 - pos].push_back(ms[i]);
+    }
+    for (int x = 0; x < 8; ++x) {
+      fseg[8 * part + x] = (int)full.size();
+      sseg[8 * part + x] = (int)sym.size();
+      for (int m : run[x]) {
+        const int T = mats[m].np / mats[m].tile;
+        for (int i = 0; i < T; ++i)
+          for (int j = 0; j < T; ++j) {
+            full.push_back(TileTask{m, (short)i, (short)j});
+            if (j >= i) sym.push_back(TileTask{m, (short)i, (short)j});
+          }
+      }
+    }
+  }
+  fseg[16] = (int)full.size();
+  sseg[16] = (int)sym.size();
+}
+
+// Buffer sizes for every matrix and the task tables.
 static void make_plan(int count, const int* n, bool with64, Plan& P) {
   P.mats.resize(count);
   size_t bytes = 0;
@@ -605,18 +687,7 @@ static void make_plan(int count, const int* n, bool with64, Plan& P) {
     bytes += 16 * align256(e * 2) + 2 * align256(e * 4) + (with64 ? 7 * align256(e * 8) : 0);
   }
   P.arena = bytes;
-  std::vector<int> order(count);
-  for (int m = 0; m < count; ++m) order[m] = m;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return P.mats[a].np > P.mats[b].np; });
-  for (int m : order) {
-    const int T = P.mats[m].np / P.mats[m].tile;
-    for (int i = 0; i < T; ++i)
-      for (int j = 0; j < T; ++j) {
-        P.full.push_back(TileTask{m, (short)i, (short)j});
-        if (j >= i) P.sym.push_back(TileTask{m, (short)i, (short)j});
-      }
-  }
+  build_tables(P.mats, P.full, P.sym, P.fseg, P.sseg);
 }
 
 static void carve(Plan& P, char* base, bool with64) {
@@ -660,6 +731,8 @@ struct Launch {
   BMat* mats;
   TileTask *full, *sym;
   int nfull, nsym;
+  const int *fseg, *sseg;   // XCD-major run bounds (17 each), device
+  int hfseg[17], hsseg[17];  // the same on the host (which launches a stage makes)
   int etiles;
   double* partials;
   int* remaining;
@@ -667,26 +740,34 @@ struct Launch {
   double c1, c2;
 };
 
+// Grouped BF16x3 stage: one launch per tile edge present (host copy hseg of the run
+// bounds decides which); grid is a multiple of 8.
+static void x3_group(const TileTask* tasks, const int* seg, const int* hseg, const BMat* mats,
+                     int op, double c1, double c2, double* partials, int grid, hipStream_t st) {
+  if (hseg[8] > hseg[0])
+    hipLaunchKernelGGL(grouped_x3_kernel<128>, dim3(grid), dim3(X3G<128>::NT), 0, st, tasks, seg,
+                       mats, op, c1, c2, partials);
+  if (hseg[16] > hseg[8])
+    hipLaunchKernelGGL(grouped_x3_kernel<64>, dim3(grid), dim3(X3G<64>::NT), 0, st, tasks, seg,
+                       mats, op, c1, c2, partials);
+}
+
 // one macro-sweep on stream st (captured into the graph, or run eagerly)
 static hipError_t macro_sweep(const Launch& L, hipStream_t st) {
-  hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(L.grid, L.nfull)), dim3(256), 0, st, L.full,
-                     L.nfull, L.mats, (int)OP_L1, 0.0, 0.0, L.partials);
-  hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(L.grid, L.nsym)), dim3(256), 0, st, L.sym,
-                     L.nsym, L.mats, (int)OP_L2, 0.0, 0.0, L.partials);
+  x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_L1, 0.0, 0.0, L.partials, L.grid, st);
+  x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_L2, 0.0, 0.0, L.partials, L.grid, st);
   if (L.refine_on) {
-    hipLaunchKernelGGL(grouped_f64_kernel, dim3(std::min(L.grid, L.nfull)), dim3(256), 0, st,
-                       L.full, L.nfull, L.mats, (int)OP_H1, L.partials);
-    hipLaunchKernelGGL(grouped_f64_kernel, dim3(std::min(L.grid, L.nsym)), dim3(256), 0, st, L.sym,
-                       L.nsym, L.mats, (int)OP_H2, L.partials);
+    hipLaunchKernelGGL(grouped_f64_kernel, dim3(L.grid), dim3(256), 0, st, L.full, L.fseg, L.mats,
+                       (int)OP_H1, L.partials);
+    hipLaunchKernelGGL(grouped_f64_kernel, dim3(L.grid), dim3(256), 0, st, L.sym, L.sseg, L.mats,
+                       (int)OP_H2, L.partials);
   }
   hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, st, L.mats, L.count, L.partials, L.order,
                      L.rule, L.max_l, L.max_h, L.refine_on, L.hist_cap, L.remaining);
   if (L.refine_on)
     hipLaunchKernelGGL(b_widen_kernel, dim3(L.etiles, L.count), dim3(256), 0, st, L.mats);
-  hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(L.grid, L.nsym)), dim3(256), 0, st, L.sym,
-                     L.nsym, L.mats, (int)OP_U3, L.c1, L.c2, L.partials);
-  hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(L.grid, L.nfull)), dim3(256), 0, st, L.full,
-                     L.nfull, L.mats, (int)OP_U4, 0.0, 0.0, L.partials);
+  x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_U3, L.c1, L.c2, L.partials, L.grid, st);
+  x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_U4, 0.0, 0.0, L.partials, L.grid, st);
   return hipGetLastError();
 }
 
@@ -761,7 +842,13 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   size_t o_stats = align256(o_rem + 64);
   size_t o_coef = align256(o_stats + 32 * (size_t)count);
   size_t o_feat = align256(o_coef + 32 * (size_t)count);
-  size_t total_meta = align256(o_feat + 32 * (size_t)count);
+  int max_n = 1;
+  for (int m = 0; m < count; ++m) max_n = std::max(max_n, n[m]);
+  const int stat_chunks = (max_n + kStatRows - 1) / kStatRows;
+  size_t o_spart = align256(o_feat + 32 * (size_t)count);
+  size_t o_fseg = align256(o_spart + 56 * (size_t)count * stat_chunks);
+  size_t o_sseg = align256(o_fseg + sizeof P.fseg);
+  size_t total_meta = align256(o_sseg + sizeof P.sseg);
   rc = grow(&g_b.meta, &g_b.meta_bytes, total_meta);
   if (rc < 0) return rc;
   char* mb = (char*)g_b.meta;
@@ -777,6 +864,8 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   BHIP_TRY(hipMemcpyAsync(mb + o_mats, P.mats.data(), sizeof(BMat) * count, hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_full, P.full.data(), sizeof(TileTask) * P.full.size(), hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_sym, P.sym.data(), sizeof(TileTask) * P.sym.size(), hipMemcpyHostToDevice, st));
+  BHIP_TRY(hipMemcpyAsync(mb + o_fseg, P.fseg, sizeof P.fseg, hipMemcpyHostToDevice, st));
+  BHIP_TRY(hipMemcpyAsync(mb + o_sseg, P.sseg, sizeof P.sseg, hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_ps, ps.data(), 8 * count, hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_pz0, pz0.data(), 8 * count, hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_pz, pz.data(), 8 * count, hipMemcpyHostToDevice, st));
@@ -798,11 +887,13 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
     cus = prop.multiProcessorCount;
   if (n_learn > 0)
-    hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(2 * cus, (int)P.sym.size())), dim3(256), 0,
-                       st, (const TileTask*)(mb + o_sym), (int)P.sym.size(), d_mats, (int)OP_S2, 0.0,
-                       0.0, (double*)nullptr);
-  hipLaunchKernelGGL(b_stats_kernel, dim3(count), dim3(256), 0, st, d_mats, d_S, d_g, d_stats,
-                     d_feat);
+    x3_group((const TileTask*)(mb + o_sym), (const int*)(mb + o_sseg), P.sseg, d_mats, OP_S2, 0.0, 0.0,
+             nullptr, 2 * cus, st);
+  double* d_spart = (double*)(mb + o_spart);
+  hipLaunchKernelGGL(b_stats_rows_kernel, dim3(stat_chunks, count), dim3(256), 0, st, d_mats, d_S,
+                     stat_chunks, d_spart);
+  hipLaunchKernelGGL(b_stats_final_kernel, dim3((count + 255) / 256), dim3(256), 0, st, d_mats,
+                     count, stat_chunks, d_spart, d_g, d_stats, d_feat);
   BHIP_TRY(hipGetLastError());
   if (n_learn > 0) {
     rc = guess_infer_batch(d_feat, count, d_coef, st);
@@ -814,16 +905,21 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   BHIP_TRY(hipGetLastError());
 
   Launch L;
+  memset(&L, 0, sizeof L);  // the struct's bytes are the graph's key
   L.mats = d_mats;
   L.full = (TileTask*)(mb + o_full);
   L.sym = (TileTask*)(mb + o_sym);
   L.nfull = (int)P.full.size();
   L.nsym = (int)P.sym.size();
+  L.fseg = (const int*)(mb + o_fseg);
+  L.sseg = (const int*)(mb + o_sseg);
+  memcpy(L.hfseg, P.fseg, sizeof L.hfseg);
+  memcpy(L.hsseg, P.sseg, sizeof L.hsseg);
   L.etiles = P.max_etiles;
   L.partials = (double*)(mb + o_part);
   L.remaining = (int*)(mb + o_rem);
   L.count = count;
-  L.grid = 2 * cus;
+  L.grid = (2 * cus + 7) / 8 * 8;  // a multiple of the 8 XCDs
   L.order = o.order;
   L.rule = o.stop;
   L.max_l = max_l;
@@ -925,7 +1021,7 @@ static int autotune_impl(const int* bucket_n, int nb, int batch, int reps, int* 
   BHIP_TRY(hipGetDevice(&dev));
   hipDeviceProp_t prop;
   BHIP_TRY(hipGetDeviceProperties(&prop, dev));
-  const int grid = 2 * prop.multiProcessorCount;
+  const int grid = (2 * prop.multiProcessorCount + 7) / 8 * 8;
   hipEvent_t e0, e1;
   BHIP_TRY(hipEventCreate(&e0));
   BHIP_TRY(hipEventCreate(&e1));
@@ -973,16 +1069,14 @@ static int autotune_impl(const int* bucket_n, int nb, int batch, int reps, int* 
         M.pbase = 0;
         M.phase = PH_LOW;
         M.action = ACT_EVAL;
-        for (int i = 0; i < tiles; ++i)
-          for (int j = 0; j < tiles; ++j) {
-            full.push_back(TileTask{m, (short)i, (short)j});
-            if (j >= i) sym.push_back(TileTask{m, (short)i, (short)j});
-          }
         p += align256(8 * tiles * (tiles + 1) / 2);
       }
+      int fseg[17], sseg[17];
+      build_tables(mats, full, sym, fseg, sseg);
       void* meta = nullptr;
       const size_t mbytes = align256(sizeof(BMat) * batch) + align256(sizeof(TileTask) * full.size()) +
-                            align256(sizeof(TileTask) * sym.size()) + align256(8 * (size_t)tiles * tiles);
+                            align256(sizeof(TileTask) * sym.size()) + align256(8 * (size_t)tiles * tiles) +
+                            2 * align256(sizeof fseg);
       if (hipMalloc(&meta, mbytes) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(buf);
@@ -994,16 +1088,18 @@ static int autotune_impl(const int* bucket_n, int nb, int batch, int reps, int* 
       TileTask* df = (TileTask*)(mp + align256(sizeof(BMat) * batch));
       TileTask* ds = (TileTask*)((char*)df + align256(sizeof(TileTask) * full.size()));
       double* dpart = (double*)((char*)ds + align256(sizeof(TileTask) * sym.size()));
+      int* dfseg = (int*)((char*)dpart + align256(8 * (size_t)tiles * tiles));
+      int* dsseg = (int*)((char*)dfseg + align256(sizeof fseg));
       (void)hipMemcpyAsync(dm, mats.data(), sizeof(BMat) * batch, hipMemcpyHostToDevice, st);
       (void)hipMemcpyAsync(df, full.data(), sizeof(TileTask) * full.size(), hipMemcpyHostToDevice, st);
       (void)hipMemcpyAsync(ds, sym.data(), sizeof(TileTask) * sym.size(), hipMemcpyHostToDevice, st);
+      (void)hipMemcpyAsync(dfseg, fseg, sizeof fseg, hipMemcpyHostToDevice, st);
+      (void)hipMemcpyAsync(dsseg, sseg, sizeof sseg, hipMemcpyHostToDevice, st);
       // every matrix uses partial base 0: timing only, the sums are discarded
       for (int r = 0; r <= reps; ++r) {
         if (r == 1) (void)hipEventRecord(e0, st);
-        hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(grid, (int)full.size())), dim3(256), 0,
-                           st, df, (int)full.size(), dm, (int)OP_L1, 0.0, 0.0, dpart);
-        hipLaunchKernelGGL(grouped_x3_kernel, dim3(std::min(grid, (int)sym.size())), dim3(256), 0,
-                           st, ds, (int)sym.size(), dm, (int)OP_L2, 0.0, 0.0, dpart);
+        x3_group(df, dfseg, fseg, dm, OP_L1, 0.0, 0.0, dpart, grid, st);
+        x3_group(ds, dsseg, sseg, dm, OP_L2, 0.0, 0.0, dpart, grid, st);
       }
       (void)hipEventRecord(e1, st);
       hipError_t he = hipEventSynchronize(e1);

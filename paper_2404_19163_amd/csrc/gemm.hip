@@ -28,19 +28,19 @@
 namespace zf {
 // SYM is a template parameter so that the two modes are distinct kernels (and show
 // up separately in a kernel trace).
-template <int BM, int BN, int BK, int WM, int WN, bool SYM, int PM>
+template <int BM, int BN, int BK, int WM, int WN, bool SYM, int PM, int NS>
 __global__ void __launch_bounds__(WM* WN * 64)
     gemm_x3_kernel(const u16* __restrict__ Ahi, const u16* __restrict__ Alo, int lda,
                    const u16* __restrict__ Bhi, const u16* __restrict__ Blo, int ldb, int K,
                    int tiles_n, int gm, EpiParams ep) {
   using C = X3Cfg<BM, BN, BK, WM, WN>;
-  __shared__ __attribute__((aligned(16))) u16 lds[2 * C::STAGE_ELEMS];
+  __shared__ __attribute__((aligned(16))) u16 lds[NS * C::STAGE_ELEMS];
   __shared__ double red[C::NT / 64];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   int ti, tj;
   tile_coords(bid, tiles_n, SYM, ti, tj, gm);
   const int mode = SYM ? (ti == tj ? 2 : 1) : 0;
-  x3_tile<BM, BN, BK, WM, WN, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, K, ti * BM, tj * BN, mode, ep,
+  x3_tile<BM, BN, BK, WM, WN, PM, NS>(Ahi, Alo, lda, Bhi, Blo, ldb, K, ti * BM, tj * BN, mode, ep,
                                   blockIdx.x, lds, red);
 }
 
@@ -136,15 +136,15 @@ int f64_blocks(int M, int N, bool sym) { return grid_blocks(M, N, f64_tile_edge(
 
 int max_blocks(int M, int N) { return grid_blocks(M, N, 64, false); }
 
-template <int BM, int BN, int WM, int WN, int PM>
+template <int BM, int BN, int WM, int WN, int PM, int NS = 2>
 static void x3_launch(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                       int ldb, int M, int N, int K, bool sym, int blocks, const EpiParams& ep,
                       hipStream_t st) {
   if (sym)
-    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, true, PM>), dim3(blocks),
+    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, true, PM, NS>), dim3(blocks),
                        dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, 1, ep);
   else
-    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, false, PM>), dim3(blocks),
+    hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, false, PM, NS>), dim3(blocks),
                        dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN,
                        tile_group(M, BM), ep);
 }
@@ -178,8 +178,8 @@ static void x3_dispatch(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi,
                         const EpiParams& ep, hipStream_t st) {
   if (tile == 256)
     x3_launch<256, 256, 2, 4, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
-  else if (tile == 128)
-    x3_launch<128, 128, 2, 2, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+  else if (tile == 128)  // 8 waves of 32 x 64 and a 3-stage ring (loads two stages ahead)
+    x3_launch<128, 128, 4, 2, PM, 3>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
   else
     x3_launch<64, 64, 2, 2, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
 }
