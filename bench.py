@@ -168,6 +168,15 @@ def main() -> int:
           f"evals={last.low_evals}+{last.high_evals} rms={last.final_rms:.3e}", file=sys.stderr,
           flush=True)
 
+    # the same steps without the per-GEMM event pairs (they cost a few µs per launch,
+    # which shows at small N)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run("bf16x3", Zm)
+    torch.cuda.synchronize()
+    mixed_noev_s = (time.perf_counter() - t0) / args.steps
+
     mixed_flops = alg_flops(n, args.order, last.low_evals + last.high_evals,
                             (last.low_evals - 1) + max(last.high_evals - 1, 0))
     value = mixed_flops / mixed_s / 1e12
@@ -265,6 +274,7 @@ def main() -> int:
                    "z0": "scaled identity", "stop": "ratio (Algorithm 2)",
                    "refine": "FP64 residual + BF16x3 correction"},
         "time_to_solution_ms": round(mixed_s * 1e3, 4),
+        "ms_per_step_without_events": round(mixed_noev_s * 1e3, 4),
         "iters": last.iters,
         "low_evals": last.low_evals,
         "high_evals": last.high_evals,
