@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 
 METRIC = ("refined-Z TFLOP/s + time-to-‖ZᵀSZ−I‖≤1e-6, mixed vs FP64 path, "
           "1 MI355X")
-PEAK_TFLOPS = {"bf16": 2500.0, "fp64": 78.6, "fp32": 157.3}
+PEAK_TFLOPS = {"bf16": 2500.0, "fp64": 78.6, "fp32": 157.3, "int8": 5000.0}
 # Sources of the GEMM kernels; an HBM-traffic record in profiles/ is used only while
 # they hash to the value it was measured with.
 GEMM_SOURCES = ["paper_2404_19163_amd/csrc/gemm.hip", "paper_2404_19163_amd/csrc/gemm_tiles.inc",
@@ -58,7 +58,7 @@ def measured_traffic(kernel: str, n: int):
 KCLASS_DTYPE = {"gemm_x3": "bf16", "gemm_x3_sym": "bf16", "gemm_f64": "fp64", "gemm_f64_sym": "fp64",
                 "gemm_hh": "bf16", "gemm_hh_sym": "bf16", "gemm_f32": "fp32", "gemm_f32_sym": "fp32",
                 "gemm_x3f16": "bf16", "gemm_x3f16_sym": "bf16", "gemm_hhf16": "bf16",
-                "gemm_hhf16_sym": "bf16"}
+                "gemm_hhf16_sym": "bf16", "gemm_oz": "int8", "gemm_oz_sym": "int8"}
 
 WORKLOADS = {
     "gauss4096": dict(n=4096, sigma=1.0,
@@ -187,6 +187,10 @@ def main() -> int:
     avg_s = tot_ms / 1e3 / max(launches, 1)
     ach = kernel_alg_flops(dom, n) / avg_s / 1e12
     peak = PEAK_TFLOPS[KCLASS_DTYPE[dom]]
+    # whole-call matrix-core fraction: sum over kernel classes of executed MFMA flops
+    # over that class's peak, divided by the measured time of the timed steps
+    mfma_s = sum(v[2] / (PEAK_TFLOPS[KCLASS_DTYPE[k]] * 1e12) for k, v in prof.items() if v[0])
+    whole_frac = mfma_s / (mixed_s * args.steps)
     kernels = {k: {"launches": v[0], "total_ms": round(v[1], 4),
                    "avg_us": round(v[1] / max(v[0], 1) * 1e3, 2),
                    "share": round(v[1] / max(mixed_s * 1e3 * args.steps, 1e-9), 4),
@@ -288,7 +292,8 @@ def main() -> int:
                      "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "copy-calibrated)",
-                     "alg_bytes": alg_bytes},
+                     "alg_bytes": alg_bytes,
+                     "whole_call_frac": round(whole_frac, 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
