@@ -255,8 +255,12 @@ def main() -> int:
         cpu_s = time.perf_counter() - t0
         cf = alg_flops(n, args.order, len(res.hist), len(res.hist) - 1)
         cores = len(os.sched_getaffinity(0))
+        try:
+            blas = np.show_config(mode="dicts")["Build Dependencies"]["blas"]["name"]
+        except Exception:  # noqa: BLE001 (older numpy: no dict mode)
+            blas = "unknown"
         cpu = {"value": round(cf / cpu_s / 1e12, 5), "unit": "TFLOP/s", "cores": cores,
-               "threads": torch.get_num_threads(), "kind": "oracle",
+               "threads": torch.get_num_threads(), "kind": "oracle", "blas": blas,
                "sample": f"{args.workload}: 2 FP64 residual evaluations + 1 update of the oracle "
                          f"recursion ({cf:.3e} alg. flops) in {cpu_s:.2f} s"}
 
