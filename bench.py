@@ -117,7 +117,7 @@ def main() -> int:
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the refinement of one matrix runs on one device and "
-              "this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+              "the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         return 2
 
     import numpy as np

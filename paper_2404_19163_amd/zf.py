@@ -73,7 +73,7 @@ def lib() -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python paper_2404_19163_amd/csrc/build.py")
     L = ctypes.CDLL(LIB_PATH)
     vp, i, d, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
     P = ctypes.POINTER

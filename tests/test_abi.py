@@ -27,7 +27,7 @@ def test_header_declares_entry_points():
 @pytest.fixture(scope="module")
 def libzf():
     if not os.path.exists(LIB):
-        pytest.fail("libzf.so is not built (run __graft_entry__.build())")
+        pytest.fail("libzf.so is not built (run python paper_2404_19163_amd/csrc/build.py)")
     return ctypes.CDLL(LIB)
 
 
