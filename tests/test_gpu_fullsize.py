@@ -143,3 +143,28 @@ def test_batched_512_learned(zf):
         else:
             assert r.flags & zf.WARN_Z0_FALLBACK
     print(f"worst rms {worst:.2e}, learned guesses {learned}/512", flush=True)
+
+
+def test_n16384_largest_order(zf):
+    """N = 16384 (the emulated residual's largest order; 2 GB per matrix): the mixed
+    refinement with the FP64 residual and with the emulated one.  The oracle checks a
+    48 x 48 block of delta = I - Z^T S Z recomputed from sampled columns (entries of size
+    RMS; bound 100 x the reported RMS), and the library's FP64 residual of the returned Z
+    against its report."""
+    n = 16384
+    S = inputs.overlap_gaussian(n, 1.0, 0)
+    Sd = _cuda(S)
+    rng = np.random.default_rng(1)
+    J = np.sort(rng.choice(n, size=48, replace=False))
+    for mode in ("f64_delta", "emu"):
+        r = zf.refine(Sd, None, precision="bf16x3", refine=mode)
+        Zs = r.Z[:, torch.from_numpy(J).cuda()].cpu().numpy()        # the sampled columns
+        block = np.eye(48) - Zs.T @ (S @ Zs)                            # delta[J, J] in FP64
+        rms64 = zf.residual(Sd, r.Z) / np.sqrt(n)
+        print(f"{mode}: {r.low_evals}+{r.high_evals} evals, reported {r.final_rms:.2e}, FP64 "
+              f"residual {rms64:.2e}, max sampled |delta| {np.max(np.abs(block)):.2e}", flush=True)
+        assert r.status == 0 and r.final_rms <= 1e-6
+        assert np.max(np.abs(block)) <= 100 * r.final_rms
+        assert rms64 == pytest.approx(r.final_rms, rel=1e-2, abs=1e-12)
+        del r
+    zf.release()
