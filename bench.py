@@ -264,6 +264,8 @@ def main() -> int:
                "sample": f"{args.workload}: 2 FP64 residual evaluations + 1 update of the oracle "
                          f"recursion ({cf:.3e} alg. flops) in {cpu_s:.2f} s"}
 
+    if cpu is not None:
+        cpu["gpu_speedup"] = round(value / cpu["value"], 1)  # same algorithmic-flop rate basis
     traffic, alg_bytes = measured_traffic(dom, n)
     line = {
         "metric": METRIC,
