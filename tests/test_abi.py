@@ -58,3 +58,28 @@ def test_version_and_default_opts(libzf):
     L.zf_default_opts(ctypes.byref(o))
     assert (o.order, o.precision, o.stop, o.max_sweeps, o.refine, o.max_refine) == (2, 1, 0, 100, 1, 10)
     assert L.zf_last_error() == b""
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """A C99 translation unit includes zf.h, takes the address of every declared entry
+    point, links against libzf.so, and calls the two pure-host functions."""
+    names = _declared()
+    src = tmp_path / "abi.c"
+    refs = ",\n  ".join(f"(void (*)(void)){n}" for n in names)
+    src.write_text(
+        "#include <stdio.h>\n#include \"zf.h\"\n"
+        f"static void (*const table[])(void) = {{\n  {refs}\n}};\n"
+        "int main(void) {\n"
+        "  zf_opts o;\n  zf_default_opts(&o);\n"
+        "  printf(\"%d %d %d %zu\\n\", zf_version(), o.order, o.precision, sizeof table / sizeof *table);\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "abi"
+    cc = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER),
+                         str(src), LIB, f"-Wl,-rpath,{os.path.dirname(LIB)}", "-o", str(exe)],
+                        capture_output=True, text=True)
+    assert cc.returncode == 0, cc.stderr
+    run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert run.returncode == 0, run.stderr
+    version, order, precision, count = run.stdout.split()
+    assert int(version) >= 1 and (int(order), int(precision)) == (2, 1)
+    assert int(count) == len(names)
