@@ -53,8 +53,9 @@ enum { OP_L1 = 0, OP_L2, OP_H1, OP_H2, OP_U3, OP_U4, OP_S2 };
 // Per-matrix record: buffers (carved from one arena) and the device-side state of
 // the recursion.  Only the DECIDE kernel writes the state.
 struct BMat {
-  int n, np, tile, tiles_sym;
-  long long pbase;  // first norm partial of this matrix
+  int n, np, tile, tiles_sym;  // BF16x3 tile edge and its upper-triangle tile count
+  int ftiles_sym;              // upper-triangle count of the 64-wide FP64 tiles
+  long long pbase;  // first norm partial of this matrix (room for the larger count)
   int phase, action, it, cur, src;
   int upd_l, upd_h, evals_l, evals_h, flags, status, hist_len;
   int learn, z0_used;  // learned guess requested; guess taken (ZF_Z0_*)
@@ -76,14 +77,12 @@ struct TileTask {
 // ---------------------------------------------------------------------------
 // BF16x3 tiles: 64- or 128-wide, 4 waves, 2-stage load ring, two blocks per CU (in
 // grouped launches this beat 8 waves with a 3-stage ring: 55.6 vs 60 ms for the
-// 512-matrix batch); one grouped launch per tile edge.  FP64 tiles: 64 or 128 wide,
-// 4 waves.
+// 512-matrix batch); one grouped launch per tile edge.  FP64 tiles: 64 wide for every
+// matrix, 4 waves.
 template <int T>
 using X3G = X3Cfg<T, T, 32, 2, 2>;
 using F64_64 = F64Cfg<64, 64, 16, 2, 2>;
-using F64_128 = F64Cfg<128, 128, 16, 2, 2>;
-static_assert(F64_64::NT == 256 && F64_128::NT == 256,
-              "the grouped FP64 kernel runs both tile bodies with one 256-thread block");
+static_assert(F64_64::NT == 256, "the grouped FP64 kernel runs 256-thread blocks");
 
 __device__ __forceinline__ bool op_applies(int op, const BMat& M) {
   const int phase = M.phase, action = M.action;
@@ -200,19 +199,21 @@ __global__ void __launch_bounds__(X3G<T>::NT, 2)
   }
 }
 
-__global__ void __launch_bounds__(256, 2)
+// FP64 stages use 64-wide tiles for every matrix (their own task tables, all in the
+// 64-wide runs): four blocks per CU, the single path's choice.
+__global__ void __launch_bounds__(256, 4)
     grouped_f64_kernel(const TileTask* __restrict__ tasks, const int* __restrict__ seg,
                        const BMat* __restrict__ mats, int op, double* partials) {
-  __shared__ double lds[2 * F64_128::STAGE];
+  __shared__ double lds[2 * F64_64::STAGE];
   __shared__ double red[4];
-  for (int part = 0; part < 2; ++part) {
   int t0, t1, step;
-  xcd_run(seg, part, t0, t1, step);
+  xcd_run(seg, 1, t0, t1, step);
   for (int t = t0; t < t1; t += step) {
     const TileTask tk = tasks[t];
     const BMat& M = mats[tk.m];
     if (!op_applies(op, M)) continue;
-    const int np = M.np, T = M.tile;
+    const int np = M.np;
+    constexpr int T = 64;
     EpiParams ep;
     memset(&ep, 0, sizeof ep);
     ep.beta = 1.0;
@@ -237,13 +238,8 @@ __global__ void __launch_bounds__(256, 2)
       const int tiles = np / T;
       pidx = tk.ti * tiles - tk.ti * (tk.ti - 1) / 2 + (tk.tj - tk.ti);
     }
-    if (T == 64)
-      f64_tile<64, 64, 16, 2, 2>(a, np, b, np, np, tk.ti * 64, tk.tj * 64, mode, ep, pidx, lds, red);
-    else
-      f64_tile<128, 128, 16, 2, 2>(a, np, b, np, np, tk.ti * 128, tk.tj * 128, mode, ep, pidx, lds,
-                                   red);
+    f64_tile<64, 64, 16, 2, 2>(a, np, b, np, np, tk.ti * 64, tk.tj * 64, mode, ep, pidx, lds, red);
     __syncthreads();
-  }
   }
 }
 
@@ -261,7 +257,8 @@ __global__ void decide_kernel(BMat* mats, int count, const double* __restrict__ 
     if (M.action == ACT_DONE) continue;
     // every matrix not yet done was evaluated in this macro-sweep
     double s = 0.0;
-    for (int t = 0; t < M.tiles_sym; ++t) s += partials[M.pbase + t];
+    const int parts = (M.phase == PH_HIGH) ? M.ftiles_sym : M.tiles_sym;  // phase just evaluated
+    for (int t = 0; t < parts; ++t) s += partials[M.pbase + t];
     const double err = sqrt(s);
     if (M.hist_len < hist_cap) M.hist[M.hist_len] = err;
     M.hist_len++;
@@ -628,6 +625,8 @@ struct Plan {
   std::vector<BMat> mats;
   std::vector<TileTask> full, sym;
   int fseg[17] = {}, sseg[17] = {};  // XCD-major run bounds of the two tables
+  std::vector<TileTask> ffull, fsym;   // FP64 tables (64-wide tiles for every matrix)
+  int ffseg[17] = {}, fsseg[17] = {};
   long long partials = 0;
   int max_etiles = 1;  // largest (np / 64)^2 of the batch: x extent of element-wise grids
   size_t arena = 0;
@@ -680,14 +679,21 @@ static void make_plan(int count, const int* n, bool with64, Plan& P) {
     M.np = rup(n[m], M.tile);
     const int T = M.np / M.tile;
     M.tiles_sym = T * (T + 1) / 2;
+    const int T64 = M.np / 64;
+    M.ftiles_sym = T64 * (T64 + 1) / 2;
     M.pbase = P.partials;
-    P.partials += M.tiles_sym;
+    P.partials += std::max(M.tiles_sym, M.ftiles_sym);
     P.max_etiles = std::max(P.max_etiles, (M.np / kET) * (M.np / kET));
     const size_t e = (size_t)M.np * M.np;
     bytes += 16 * align256(e * 2) + 2 * align256(e * 4) + (with64 ? 7 * align256(e * 8) : 0);
   }
   P.arena = bytes;
   build_tables(P.mats, P.full, P.sym, P.fseg, P.sseg);
+  if (with64) {
+    std::vector<BMat> m64 = P.mats;
+    for (BMat& M : m64) M.tile = 64;
+    build_tables(m64, P.ffull, P.fsym, P.ffseg, P.fsseg);
+  }
 }
 
 static void carve(Plan& P, char* base, bool with64) {
@@ -733,6 +739,8 @@ struct Launch {
   int nfull, nsym;
   const int *fseg, *sseg;   // XCD-major run bounds (17 each), device
   int hfseg[17], hsseg[17];  // the same on the host (which launches a stage makes)
+  TileTask *ffull, *fsym;    // FP64 tables and their run bounds (device)
+  const int *ffseg, *fsseg;
   int etiles;
   double* partials;
   int* remaining;
@@ -757,10 +765,11 @@ static hipError_t macro_sweep(const Launch& L, hipStream_t st) {
   x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_L1, 0.0, 0.0, L.partials, L.grid, st);
   x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_L2, 0.0, 0.0, L.partials, L.grid, st);
   if (L.refine_on) {
-    hipLaunchKernelGGL(grouped_f64_kernel, dim3(L.grid), dim3(256), 0, st, L.full, L.fseg, L.mats,
-                       (int)OP_H1, L.partials);
-    hipLaunchKernelGGL(grouped_f64_kernel, dim3(L.grid), dim3(256), 0, st, L.sym, L.sseg, L.mats,
-                       (int)OP_H2, L.partials);
+    // 64-wide FP64 tiles fit four blocks per CU: twice the grid
+    hipLaunchKernelGGL(grouped_f64_kernel, dim3(2 * L.grid), dim3(256), 0, st, L.ffull, L.ffseg,
+                       L.mats, (int)OP_H1, L.partials);
+    hipLaunchKernelGGL(grouped_f64_kernel, dim3(2 * L.grid), dim3(256), 0, st, L.fsym, L.fsseg,
+                       L.mats, (int)OP_H2, L.partials);
   }
   hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, st, L.mats, L.count, L.partials, L.order,
                      L.rule, L.max_l, L.max_h, L.refine_on, L.hist_cap, L.remaining);
@@ -848,7 +857,11 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   size_t o_spart = align256(o_feat + 32 * (size_t)count);
   size_t o_fseg = align256(o_spart + 56 * (size_t)count * stat_chunks);
   size_t o_sseg = align256(o_fseg + sizeof P.fseg);
-  size_t total_meta = align256(o_sseg + sizeof P.sseg);
+  size_t o_ffull = align256(o_sseg + sizeof P.sseg);
+  size_t o_fsym = align256(o_ffull + sizeof(TileTask) * P.ffull.size());
+  size_t o_ffseg = align256(o_fsym + sizeof(TileTask) * P.fsym.size());
+  size_t o_fsseg = align256(o_ffseg + sizeof P.ffseg);
+  size_t total_meta = align256(o_fsseg + sizeof P.fsseg);
   rc = grow(&g_b.meta, &g_b.meta_bytes, total_meta);
   if (rc < 0) return rc;
   char* mb = (char*)g_b.meta;
@@ -866,6 +879,14 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   BHIP_TRY(hipMemcpyAsync(mb + o_sym, P.sym.data(), sizeof(TileTask) * P.sym.size(), hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_fseg, P.fseg, sizeof P.fseg, hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_sseg, P.sseg, sizeof P.sseg, hipMemcpyHostToDevice, st));
+  if (with64) {
+    BHIP_TRY(hipMemcpyAsync(mb + o_ffull, P.ffull.data(), sizeof(TileTask) * P.ffull.size(),
+                            hipMemcpyHostToDevice, st));
+    BHIP_TRY(hipMemcpyAsync(mb + o_fsym, P.fsym.data(), sizeof(TileTask) * P.fsym.size(),
+                            hipMemcpyHostToDevice, st));
+    BHIP_TRY(hipMemcpyAsync(mb + o_ffseg, P.ffseg, sizeof P.ffseg, hipMemcpyHostToDevice, st));
+    BHIP_TRY(hipMemcpyAsync(mb + o_fsseg, P.fsseg, sizeof P.fsseg, hipMemcpyHostToDevice, st));
+  }
   BHIP_TRY(hipMemcpyAsync(mb + o_ps, ps.data(), 8 * count, hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_pz0, pz0.data(), 8 * count, hipMemcpyHostToDevice, st));
   BHIP_TRY(hipMemcpyAsync(mb + o_pz, pz.data(), 8 * count, hipMemcpyHostToDevice, st));
@@ -915,6 +936,10 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   L.sseg = (const int*)(mb + o_sseg);
   memcpy(L.hfseg, P.fseg, sizeof L.hfseg);
   memcpy(L.hsseg, P.sseg, sizeof L.hsseg);
+  L.ffull = (TileTask*)(mb + o_ffull);
+  L.fsym = (TileTask*)(mb + o_fsym);
+  L.ffseg = (const int*)(mb + o_ffseg);
+  L.fsseg = (const int*)(mb + o_fsseg);
   L.etiles = P.max_etiles;
   L.partials = (double*)(mb + o_part);
   L.remaining = (int*)(mb + o_rem);
