@@ -132,6 +132,16 @@ static int tile_group(int M, int t) {
   return (gm > 1 && (M / t) % gm == 0) ? gm : 1;
 }
 
+// Band height of the symmetric-grid tile order: 4 (a run of 17 of the 136 tiles of
+// an N = 4096 triangle then spans about 4 x 5 tiles instead of one tile row; the
+// symmetric BF16x3 GEMM measured 308 -> 303 us); ZF_SYM_TILE_GROUP overrides (1: row
+// by row).
+static int sym_group() {
+  const char* env = getenv("ZF_SYM_TILE_GROUP");
+  const int g = env ? atoi(env) : 4;
+  return g >= 1 ? g : 1;
+}
+
 int f64_blocks(int M, int N, bool sym) { return grid_blocks(M, N, f64_tile_edge(M, N, sym), sym); }
 
 int max_blocks(int M, int N) { return grid_blocks(M, N, 64, false); }
@@ -142,7 +152,7 @@ static void x3_launch(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, c
                       hipStream_t st) {
   if (sym)
     hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, true, PM, NS>), dim3(blocks),
-                       dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, 1, ep);
+                       dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym_group(), ep);
   else
     hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, false, PM, NS>), dim3(blocks),
                        dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN,
@@ -154,7 +164,7 @@ static void f32_launch(const float* A, int lda, const float* B, int ldb, int M, 
                        bool sym, int blocks, const EpiParams& ep, hipStream_t st) {
   if (sym)
     hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, true>), dim3(blocks), dim3(WM * WN * 64),
-                       0, st, A, lda, B, ldb, K, N / BN, 1, ep);
+                       0, st, A, lda, B, ldb, K, N / BN, sym_group(), ep);
   else
     hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, false>), dim3(blocks), dim3(WM * WN * 64),
                        0, st, A, lda, B, ldb, K, N / BN, tile_group(M, BM), ep);
@@ -165,7 +175,7 @@ static void f64_launch(const double* A, int lda, const double* B, int ldb, int M
                        bool sym, int blocks, const EpiParams& ep, hipStream_t st) {
   if (sym)
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, 16, WM, WN, true>), dim3(blocks),
-                       dim3(WM * WN * 64), 0, st, A, lda, B, ldb, K, N / BN, 1, ep);
+                       dim3(WM * WN * 64), 0, st, A, lda, B, ldb, K, N / BN, sym_group(), ep);
   else
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, 16, WM, WN, false>), dim3(blocks),
                        dim3(WM * WN * 64), 0, st, A, lda, B, ldb, K, N / BN, tile_group(M, BM),
