@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(WM* WN * 64)
   tile_coords(bid, tiles_n, SYM, ti, tj, gm);
   const int mode = SYM ? (ti == tj ? 2 : 1) : 0;
   x3_tile<BM, BN, BK, WM, WN, PM, NS>(Ahi, Alo, lda, Bhi, Blo, ldb, K, ti * BM, tj * BN, mode, ep,
-                                  blockIdx.x, lds, red);
+                                  tile_index(ti, tj, tiles_n, SYM), lds, red);
 }
 
 // FP32 matrix-core GEMM ("single"): f32_mainloop + the shared epilogue.
@@ -62,7 +62,8 @@ __global__ void __launch_bounds__(WM* WN * 64)
 #pragma unroll
     for (int b = 0; b < C::FN; ++b) acc[a][b] = f32x16{};
   f32_mainloop<BM, BN, WM, WN>(A, lda, B, ldb, 0, K, ti * BM, tj * BN, lds, acc);
-  x3_epilogue<BM, BN, 32, WM, WN>(acc, ti * BM, tj * BN, mode, ep, blockIdx.x, lds, red);
+  x3_epilogue<BM, BN, 32, WM, WN>(acc, ti * BM, tj * BN, mode, ep, tile_index(ti, tj, tiles_n, SYM),
+                                  lds, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -79,7 +80,8 @@ __global__ void __launch_bounds__(WM* WN * 64, 2)
   int ti, tj;
   tile_coords(bid, tiles_n, SYM, ti, tj, gm);
   const int mode = SYM ? (ti == tj ? 2 : 1) : 0;
-  f64_tile<BM, BN, BK, WM, WN>(A, lda, B, ldb, K, ti * BM, tj * BN, mode, ep, blockIdx.x, lds, red);
+  f64_tile<BM, BN, BK, WM, WN>(A, lda, B, ldb, K, ti * BM, tj * BN, mode, ep,
+                               tile_index(ti, tj, tiles_n, SYM), lds, red);
 }
 
 // ---------------------------------------------------------------------------

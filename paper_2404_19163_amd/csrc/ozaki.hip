@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(WM* WN * 64, 2)
         epi_group(ep, row0, col, v, mode, nsum);
       }
     }
-  if (ep.partials) block_norm_store<C::NT>(nsum, ep.partials, blockIdx.x, red);
+  if (ep.partials) block_norm_store<C::NT>(nsum, ep.partials, tile_index(ti, tj, tiles_n, SYM), red);
 }
 
 static int oz_grid(int np, int t, bool sym) {
