@@ -232,7 +232,7 @@ def main() -> int:
         emu_s = (time.perf_counter() - t0) / args.fp64_steps
         emu = {"ms": round(emu_s * 1e3, 3), "evals": [re_.low_evals, re_.high_evals],
                "final_rms": re_.final_rms, "slices": int(os.environ.get("ZF_EMU_SLICES", "7")),
-               "fp64_rms": zf.residual(S, Ze) / math.sqrt(n)}
+               "fp64_rms": zf.residual(S, Ze)}
         print(f"[bench] mixed, emulated FP64 residual: {emu_s * 1e3:.3f} ms/step "
               f"rms={re_.final_rms:.3e}", file=sys.stderr, flush=True)
 

@@ -100,8 +100,10 @@ typedef struct {
   int max_sweeps; /* cap on Z updates in the first phase; <= 0 means 100                */
   int refine;     /* enum zf_refine_mode; ignored for ZF_FP64                            */
   int max_refine; /* cap on Z updates in the refinement phase; <= 0 means 10             */
-  int z0;         /* guess when Z0 is NULL: 0 scaled identity, 1 learned (zf_mlp_*) with the
-                     scaled identity as fallback                                          */
+  int z0;         /* enum zf_z0_kind: the guess when Z0 is NULL.  ZF_Z0_SCALED_IDENTITY
+                     (default) or ZF_Z0_LEARNED (zf_mlp_*, scaled identity as fallback).
+                     A non-NULL Z0 is always used as given; ZF_Z0_GIVEN with Z0 == NULL
+                     is ZF_ERR_ARG.                                                       */
 } zf_opts;
 
 typedef struct {
@@ -151,9 +153,10 @@ int zf_refine_ex(const double* S, const double* Z0, int n, const zf_opts* opts, 
  *   S[m], Z[m]  device pointers (host arrays of count pointers), n[m] x n[m] FP64, n[m] in
  *               1..8192; Z0 may be NULL (all scaled identity) or hold NULL entries.
  *   opts        order must be 2, precision ZF_BF16X3, refine ZF_REFINE_OFF or
- *               ZF_REFINE_F64_DELTA (opts NULL = defaults).  opts.z0 = 1 gives every
- *               matrix without a Z0 the learned guess (per-matrix acceptance on the
- *               device, scaled-identity fallback flagged in its result).
+ *               ZF_REFINE_F64_DELTA (opts NULL = defaults).  opts.z0 = ZF_Z0_LEARNED
+ *               gives every matrix without a Z0 the learned guess (per-matrix
+ *               acceptance on the device, scaled-identity fallback flagged in its
+ *               result); ZF_Z0_GIVEN requires a Z0 for every matrix.
  *   res         host[count] or NULL: per-matrix result including status.
  *   hist        host[count * hist_cap]: matrix m's residual history at m * hist_cap.
  * Every matrix runs the recursion and stop test of zf_refine_ex; the matrices advance
@@ -195,7 +198,7 @@ void zf_batched_release(void);
  * max(g_lo,0)/g, g_lo/g, mean_i sum_j |S_ij| / g, with g_lo the Gershgorin lower bound.
  * Network: 8 -> 64 -> 64 -> 3, tanh, FP32, 4931 parameters in the order W1 (64x8), b1,
  * W2 (64x64), b2, W3 (3x64), b3; inputs and outputs standardized by zf_mlp_set_norm.
- * With opts.z0 = 1 and Z0 == NULL, zf_refine_ex predicts (c0, c1, c2), rescales them so
+ * With opts.z0 = ZF_Z0_LEARNED and Z0 == NULL, zf_refine_ex predicts (c0, c1, c2), rescales them so
  * that max x p(x)^2 <= 1.9 on the Gershgorin interval [max(g_lo,0)/g, 1], and falls back
  * to the scaled identity (ZF_WARN_Z0_FALLBACK) if p <= 0 there or no network is loaded.
  */
@@ -244,9 +247,13 @@ int zf_mlp_predict(const float* feats, double* coef_host, void* stream);
 int zf_congruence(const double* H, const double* Z, int n, int precision, double* Hp,
                   void* stream);
 
-/* zf_residual -- err_f = ||Z^T S Z - I||_F evaluated with FP64 products (host double).
- * S, Z: device n x n FP64. */
-int zf_residual(const double* S, const double* Z, int n, double* err_f, void* stream);
+/* zf_residual -- rms = ||Z^T S Z - I||_F / sqrt(n), the residual every result is judged
+ * by, evaluated with the FP64 matrix-core products of the refinement phase (Sec. IV.B:
+ * S Z, then the symmetric Z^T (S Z), and a fixed-order FP64 sum of squares).
+ *   S, Z: device n x n FP64 (S symmetric), read only.  rms: host double.
+ * Synchronizes the stream.  Errors: ZF_ERR_ARG (NULL pointer, n < 1), ZF_ERR_NOMEM,
+ * ZF_ERR_HIP. */
+int zf_residual(const double* S, const double* Z, int n, double* rms, void* stream);
 
 /* zf_release -- free every cached workspace of the current device. */
 void zf_release(void);

@@ -67,11 +67,6 @@ struct BMat {
   double *s64, *z64r[2], *z64c[2], *a64t, *d64;
 };
 
-struct TileTask {
-  int m;
-  short ti, tj;
-};
-
 // ---------------------------------------------------------------------------
 // grouped GEMMs
 // ---------------------------------------------------------------------------
@@ -632,39 +627,15 @@ struct Plan {
   size_t arena = 0;
 };
 
-// XCD-major task tables (see xcd_run): per tile edge, matrices go to the 8 XCDs in
-// snake order of decreasing order n (each XCD gets a like mix of sizes); within a run,
-// matrices by decreasing n, each matrix's tiles consecutive.
+// XCD-major task tables (see xcd_run) of the matrices' padded orders and tile edges.
 static void build_tables(const std::vector<BMat>& mats, std::vector<TileTask>& full,
                          std::vector<TileTask>& sym, int* fseg, int* sseg) {
-  full.clear();
-  sym.clear();
-  for (int part = 0; part < 2; ++part) {
-    const int edge = part == 0 ? 128 : 64;
-    std::vector<int> ms;
-    for (int m = 0; m < (int)mats.size(); ++m)
-      if (mats[m].tile == edge) ms.push_back(m);
-    std::stable_sort(ms.begin(), ms.end(), [&](int a, int b) { return mats[a].np > mats[b].np; });
-    std::vector<int> run[8];
-    for (int i = 0; i < (int)ms.size(); ++i) {
-      const int r = i / 8, pos = i % 8;
-      run[(r % 2 == 0) ? pos : 7 - pos].push_back(ms[i]);
-    }
-    for (int x = 0; x < 8; ++x) {
-      fseg[8 * part + x] = (int)full.size();
-      sseg[8 * part + x] = (int)sym.size();
-      for (int m : run[x]) {
-        const int T = mats[m].np / mats[m].tile;
-        for (int i = 0; i < T; ++i)
-          for (int j = 0; j < T; ++j) {
-            full.push_back(TileTask{m, (short)i, (short)j});
-            if (j >= i) sym.push_back(TileTask{m, (short)i, (short)j});
-          }
-      }
-    }
+  std::vector<int> np(mats.size()), tile(mats.size());
+  for (size_t m = 0; m < mats.size(); ++m) {
+    np[m] = mats[m].np;
+    tile[m] = mats[m].tile;
   }
-  fseg[16] = (int)full.size();
-  sseg[16] = (int)sym.size();
+  build_task_tables((int)mats.size(), np.data(), tile.data(), full, sym, fseg, sseg);
 }
 
 // Buffer sizes for every matrix and the task tables.
@@ -793,11 +764,14 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   if (o.stop != ZF_STOP_RATIO && o.stop != ZF_STOP_MONOTONE)
     return set_error(ZF_ERR_ARG, "unknown stop rule %d", o.stop);
   if (hist_cap < 0 || (hist_cap > 0 && !hist)) return set_error(ZF_ERR_ARG, "bad hist buffer");
-  if (o.z0 != 0 && o.z0 != 1) return set_error(ZF_ERR_ARG, "unknown guess kind %d", o.z0);
+  if (o.z0 != ZF_Z0_GIVEN && o.z0 != ZF_Z0_SCALED_IDENTITY && o.z0 != ZF_Z0_LEARNED)
+    return set_error(ZF_ERR_ARG, "unknown guess kind %d", o.z0);
   for (int m = 0; m < count; ++m) {
     if (n[m] <= 0 || n[m] > 8192)
       return set_error(ZF_ERR_ARG, "matrix %d: order %d outside 1..8192", m, n[m]);
     if (!S[m] || !Z[m]) return set_error(ZF_ERR_ARG, "matrix %d: NULL S or Z", m);
+    if (o.z0 == ZF_Z0_GIVEN && !(Z0 && Z0[m]))
+      return set_error(ZF_ERR_ARG, "matrix %d: opts.z0 = ZF_Z0_GIVEN needs its Z0", m);
   }
   const bool with64 = o.refine == ZF_REFINE_F64_DELTA;
   const int max_l = o.max_sweeps > 0 ? o.max_sweeps : 100;
@@ -815,7 +789,7 @@ static int batched_impl(int count, const double* const* S, const double* const* 
 
   Plan P;
   make_plan(count, n, with64, P);
-  // guesses: given where Z0[m] is set, else learned (opts.z0 = 1, network loaded; the
+  // guesses: given where Z0[m] is set, else learned (opts.z0 = ZF_Z0_LEARNED, network loaded; the
   // device may still fall back) or the scaled identity
   const bool have_net = net_ready();
   int n_learn = 0;
@@ -823,13 +797,13 @@ static int batched_impl(int count, const double* const* S, const double* const* 
     BMat& M = P.mats[m];
     if (Z0 && Z0[m]) {
       M.z0_used = ZF_Z0_GIVEN;
-    } else if (o.z0 == 1 && have_net) {
+    } else if (o.z0 == ZF_Z0_LEARNED && have_net) {
       M.learn = 1;
       M.z0_used = ZF_Z0_LEARNED;
       ++n_learn;
     } else {
       M.z0_used = ZF_Z0_SCALED_IDENTITY;
-      if (o.z0 == 1) M.flags |= ZF_WARN_Z0_FALLBACK;
+      if (o.z0 == ZF_Z0_LEARNED) M.flags |= ZF_WARN_Z0_FALLBACK;
     }
   }
   int rc = grow(&g_b.arena, &g_b.arena_bytes, std::max<size_t>(P.arena, 256));

@@ -21,10 +21,14 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "zf.h"
+#include "zf_index.h"
 #include "zf_internal.h"
 
 namespace zf {
@@ -42,6 +46,45 @@ int set_error(int code, const char* fmt, ...) {
 }
 
 void clear_error() { g_err.clear(); }
+
+// ---------------------------------------------------------------------------
+// tracing: JSON lines (ZF_LOG) and roctx ranges
+// ---------------------------------------------------------------------------
+static FILE* g_log = nullptr;
+static std::string g_log_path;
+
+bool log_on() {
+  const char* v = getenv("ZF_LOG");
+  if (!v || !*v || strcmp(v, "0") == 0) return false;
+  if (strcmp(v, "1") == 0) {
+    if (g_log && g_log != stderr) fclose(g_log);
+    g_log = stderr;
+    g_log_path.clear();
+    return true;
+  }
+  if (g_log && g_log != stderr && g_log_path == v) return true;
+  if (g_log && g_log != stderr) fclose(g_log);
+  g_log = fopen(v, "a");
+  g_log_path = g_log ? v : "";
+  return g_log != nullptr;
+}
+
+void log_line(const char* fmt, ...) {
+  if (!g_log) return;
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  fprintf(g_log, "{%s}\n", buf);
+  fflush(g_log);
+}
+
+TraceRange::TraceRange(const char* name) { roctxRangePushA(name); }
+void TraceRange::end() {
+  if (live) roctxRangePop();
+  live = false;
+}
 
 #define fail set_error
 
@@ -179,6 +222,87 @@ static int ws_alloc(Workspace& w, T** out, size_t elems) {
   return 0;
 }
 
+// Allocate every buffer of a workspace for order np with the given parts.  On any
+// failure the partly built workspace is freed again and the error returned.
+static int ws_build(Workspace& w, int dev, int np, bool x3, bool f64, bool f32, bool oz) {
+  w.device = dev;
+  w.np = np;
+  w.has_x3 = x3;
+  w.has_f64 = f64;
+  w.has_f32 = f32;
+  w.has_oz = oz;
+  const size_t m = (size_t)np * np;
+  const int tiles = max_blocks(np, np);
+  ZF_TRY(ws_alloc(w, &w.partials, tiles));
+  ZF_TRY(ws_alloc(w, &w.err_dev, 8));
+  ZF_TRY(ws_alloc(w, &w.rowsum, np));
+  ZF_TRY(ws_alloc(w, &w.g_dev, 8));
+  ZF_TRY(ws_alloc(w, &w.gscr, 8192));
+  ZF_TRY(ws_alloc(w, &w.cg, 8));
+  ZF_TRY(ws_alloc(w, &w.feats, 64));
+  if (hipHostMalloc((void**)&w.host_err, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    w.host_err = nullptr;
+    return fail(ZF_ERR_NOMEM, "hipHostMalloc of the pinned norm word failed");
+  }
+  // the BF16 pairs of delta and Q and the row-major Z pair serve both phases
+  ZF_TRY(ws_alloc(w, &w.d_hi, m));
+  ZF_TRY(ws_alloc(w, &w.d_lo, m));
+  ZF_TRY(ws_alloc(w, &w.q_hi, m));
+  ZF_TRY(ws_alloc(w, &w.q_lo, m));
+  ZF_TRY(ws_alloc(w, &w.u_hi, m));
+  ZF_TRY(ws_alloc(w, &w.u_lo, m));
+  for (int b = 0; b < 2; ++b) {
+    ZF_TRY(ws_alloc(w, &w.zr_hi[b], m));
+    ZF_TRY(ws_alloc(w, &w.zr_lo[b], m));
+  }
+  if (x3) {
+    ZF_TRY(ws_alloc(w, &w.s_hi, m));
+    ZF_TRY(ws_alloc(w, &w.s_lo, m));
+    ZF_TRY(ws_alloc(w, &w.at_hi, m));
+    ZF_TRY(ws_alloc(w, &w.at_lo, m));
+    for (int b = 0; b < 2; ++b) {
+      ZF_TRY(ws_alloc(w, &w.zc_hi[b], m));
+      ZF_TRY(ws_alloc(w, &w.zc_lo[b], m));
+    }
+  }
+  if (x3 || f32)
+    for (int b = 0; b < 2; ++b) ZF_TRY(ws_alloc(w, &w.z32[b], m));
+  if (f32) {
+    ZF_TRY(ws_alloc(w, &w.s32, m));
+    ZF_TRY(ws_alloc(w, &w.a32t, m));
+    ZF_TRY(ws_alloc(w, &w.dl32, m));
+    ZF_TRY(ws_alloc(w, &w.q32, m));
+    ZF_TRY(ws_alloc(w, &w.u32, m));
+    for (int b = 0; b < 2; ++b) ZF_TRY(ws_alloc(w, &w.zc32[b], m));
+  }
+  if (f64) {
+    ZF_TRY(ws_alloc(w, &w.s64, m));
+    ZF_TRY(ws_alloc(w, &w.a64t, m));
+    ZF_TRY(ws_alloc(w, &w.d64, m));
+    ZF_TRY(ws_alloc(w, &w.q64, m));
+    ZF_TRY(ws_alloc(w, &w.u64, m));
+    for (int b = 0; b < 2; ++b) {
+      ZF_TRY(ws_alloc(w, &w.z64r[b], m));
+      ZF_TRY(ws_alloc(w, &w.z64c[b], m));
+    }
+  }
+  if (oz) {
+    ZF_TRY(ws_alloc(w, &w.oz_s, m * kOzMaxSlices));
+    ZF_TRY(ws_alloc(w, &w.oz_z, m * kOzMaxSlices));
+    ZF_TRY(ws_alloc(w, &w.oz_a, m * kOzMaxSlices));
+    ZF_TRY(ws_alloc(w, &w.oz_es, np));
+    ZF_TRY(ws_alloc(w, &w.oz_ez, np));
+    ZF_TRY(ws_alloc(w, &w.oz_ea, np));
+  }
+  return 0;
+}
+
+// The cached workspace of the current device, grown (never shrunk) to order np and
+// the requested parts.  The old buffers are released before the new ones are
+// allocated (at large n both would not fit).  If an allocation fails, every buffer
+// of the new workspace is released and the cache is left empty (np = 0, no parts),
+// so the next call allocates afresh instead of reusing null pointers.
 static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out, bool need_f32 = false,
                   bool need_oz = false) {
   int dev = 0;
@@ -186,78 +310,21 @@ static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out, bool nee
   Workspace& w = g_ws;
   if (w.device != dev || w.np < np || (need_x3 && !w.has_x3) || (need_f64 && !w.has_f64) ||
       (need_f32 && !w.has_f32) || (need_oz && !w.has_oz)) {
-    const bool keep_x3 = (w.device == dev) && w.has_x3;
-    const bool keep_f64 = (w.device == dev) && w.has_f64;
-    const bool keep_f32 = (w.device == dev) && w.has_f32;
-    const bool keep_oz = (w.device == dev) && w.has_oz;
-    const int np_new = (w.device == dev && w.np > np) ? w.np : np;
+    const bool same = w.device == dev;
+    const bool x3 = need_x3 || (same && w.has_x3);
+    const bool f64 = need_f64 || (same && w.has_f64);
+    const bool f32 = need_f32 || (same && w.has_f32);
+    const bool oz = need_oz || (same && w.has_oz);
+    const int np_new = (same && w.np > np) ? w.np : np;
     ws_free(w);
-    w.device = dev;
-    w.np = np_new;
-    const size_t m = (size_t)np_new * np_new;
-    const int tiles = max_blocks(np_new, np_new);
-    w.has_x3 = need_x3 || keep_x3;
-    w.has_f64 = need_f64 || keep_f64;
-    w.has_f32 = need_f32 || keep_f32;
-    w.has_oz = need_oz || keep_oz;
-    ZF_TRY(ws_alloc(w, &w.partials, tiles));
-    ZF_TRY(ws_alloc(w, &w.err_dev, 8));
-    ZF_TRY(ws_alloc(w, &w.rowsum, np_new));
-    ZF_TRY(ws_alloc(w, &w.g_dev, 8));
-    ZF_TRY(ws_alloc(w, &w.gscr, 8192));
-    ZF_TRY(ws_alloc(w, &w.cg, 8));
-    ZF_TRY(ws_alloc(w, &w.feats, 64));
-    HIP_TRY(hipHostMalloc((void**)&w.host_err, 8 * sizeof(double), hipHostMallocDefault));
-    // the BF16 pairs of delta and Q and the row-major Z pair serve both phases
-    ZF_TRY(ws_alloc(w, &w.d_hi, m));
-    ZF_TRY(ws_alloc(w, &w.d_lo, m));
-    ZF_TRY(ws_alloc(w, &w.q_hi, m));
-    ZF_TRY(ws_alloc(w, &w.q_lo, m));
-    ZF_TRY(ws_alloc(w, &w.u_hi, m));
-    ZF_TRY(ws_alloc(w, &w.u_lo, m));
-    for (int b = 0; b < 2; ++b) {
-      ZF_TRY(ws_alloc(w, &w.zr_hi[b], m));
-      ZF_TRY(ws_alloc(w, &w.zr_lo[b], m));
+    w.device = -1;
+    Workspace nw;
+    const int rc = ws_build(nw, dev, np_new, x3, f64, f32, oz);
+    if (rc < 0) {
+      ws_free(nw);
+      return rc;
     }
-    if (w.has_x3) {
-      ZF_TRY(ws_alloc(w, &w.s_hi, m));
-      ZF_TRY(ws_alloc(w, &w.s_lo, m));
-      ZF_TRY(ws_alloc(w, &w.at_hi, m));
-      ZF_TRY(ws_alloc(w, &w.at_lo, m));
-      for (int b = 0; b < 2; ++b) {
-        ZF_TRY(ws_alloc(w, &w.zc_hi[b], m));
-        ZF_TRY(ws_alloc(w, &w.zc_lo[b], m));
-      }
-    }
-    if (w.has_x3 || w.has_f32)
-      for (int b = 0; b < 2; ++b) ZF_TRY(ws_alloc(w, &w.z32[b], m));
-    if (w.has_f32) {
-      ZF_TRY(ws_alloc(w, &w.s32, m));
-      ZF_TRY(ws_alloc(w, &w.a32t, m));
-      ZF_TRY(ws_alloc(w, &w.dl32, m));
-      ZF_TRY(ws_alloc(w, &w.q32, m));
-      ZF_TRY(ws_alloc(w, &w.u32, m));
-      for (int b = 0; b < 2; ++b) ZF_TRY(ws_alloc(w, &w.zc32[b], m));
-    }
-    if (w.has_f64) {
-      ZF_TRY(ws_alloc(w, &w.s64, m));
-      ZF_TRY(ws_alloc(w, &w.a64t, m));
-      ZF_TRY(ws_alloc(w, &w.d64, m));
-      ZF_TRY(ws_alloc(w, &w.q64, m));
-      ZF_TRY(ws_alloc(w, &w.u64, m));
-      for (int b = 0; b < 2; ++b) {
-        ZF_TRY(ws_alloc(w, &w.z64r[b], m));
-        ZF_TRY(ws_alloc(w, &w.z64c[b], m));
-      }
-    }
-    if (w.has_oz) {
-      ZF_TRY(ws_alloc(w, &w.oz_s, m * kOzMaxSlices));
-      ZF_TRY(ws_alloc(w, &w.oz_z, m * kOzMaxSlices));
-      ZF_TRY(ws_alloc(w, &w.oz_a, m * kOzMaxSlices));
-      ZF_TRY(ws_alloc(w, &w.oz_es, np_new));
-      ZF_TRY(ws_alloc(w, &w.oz_ez, np_new));
-      ZF_TRY(ws_alloc(w, &w.oz_ea, np_new));
-    }
+    w = nw;
   }
   *out = &w;
   return 0;
@@ -388,6 +455,7 @@ struct Ctx {
   double sigma;     // power-of-two scale of the FP16 delta pairs (FP16 halves only)
   int oz_slices = 7;     // slices per operand of the emulated residual
   bool oz_s_ready = false;  // S's slices are in the workspace (once per call)
+  bool log = false;         // ZF_LOG: one JSON line per residual evaluation
 };
 
 static void series(int m, double* c) {
@@ -583,19 +651,28 @@ static int run_phase(Ctx& c, Arith da, Arith ca, bool high, int stop_rule, int m
                      int& cur, std::vector<double>& hist, PhaseOut& out) {
   static const char* kName[7] = {"BF16x3", "BF16",   "FP32",         "FP64",
                                  "FP16x3", "FP16", "emulated FP64"};
+  TraceRange phase_range(high ? "zf.phase_high" : "zf.phase_low");
   double prev = 0.0;
   for (int it = 0;; ++it) {
     double err = 0.0;
-    ZF_TRY(delta_eval(c, da, ca, cur, &err));
+    {
+      TraceRange r("zf.residual_eval");
+      ZF_TRY(delta_eval(c, da, ca, cur, &err));
+    }
     out.evals++;
     hist.push_back(err);
-    if (!isfinite(err))
-      return fail(ZF_ERR_NONFINITE, "residual norm is not finite at %s sweep %d", kName[da], it);
     bool stop = false;
-    if (it > 0) {
+    if (it > 0 && isfinite(err)) {
       if (stop_rule == ZF_STOP_MONOTONE) stop = err >= prev;
       else stop = err > pow(prev, (double)(c.order + 1));
     }
+    if (c.log)
+      log_line("\"event\": \"eval\", \"n\": %d, \"arith\": \"%s\", \"phase\": \"%s\", \"it\": %d, "
+               "\"err_f\": %.17g, \"rms\": %.6e, \"stop\": %s",
+               c.n, kName[da], high ? "high" : "low", it, err, err / sqrt((double)c.n),
+               stop ? "true" : "false");
+    if (!isfinite(err))
+      return fail(ZF_ERR_NONFINITE, "residual norm is not finite at %s sweep %d", kName[da], it);
     if (stop) {
       if (err > prev) {  // the previous iterate is still in the other buffer
         cur ^= 1;
@@ -613,7 +690,10 @@ static int run_phase(Ctx& c, Arith da, Arith ca, bool high, int stop_rule, int m
       out.capped = true;
       return 0;
     }
-    ZF_TRY(update(c, da, ca, high, cur));
+    {
+      TraceRange r("zf.update");
+      ZF_TRY(update(c, da, ca, high, cur));
+    }
     cur ^= 1;
     prev = err;
   }
@@ -671,8 +751,8 @@ static int oz_slices_env() {
   return (v >= 3 && v <= kOzMaxSlices) ? v : 7;
 }
 
-static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& o, double* Z,
-                       zf_result* res, double* hist, int hist_cap, hipStream_t st) {
+static int refine_core(const double* S, const double* Z0, int n, const zf_opts& o, double* Z,
+                       zf_result* res, double* hist, int hist_cap, hipStream_t st, bool log) {
   if (!S || !Z) return fail(ZF_ERR_ARG, "S and Z must be non-NULL device pointers");
   if (n <= 0) return fail(ZF_ERR_ARG, "n must be >= 1 (got %d)", n);
   if (o.order < 1 || o.order > 5) return fail(ZF_ERR_ARG, "order must be in 1..5 (got %d)", o.order);
@@ -686,7 +766,9 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
     return fail(ZF_ERR_ARG, "the emulated FP64 residual supports n <= %d (got %d)", kOzMaxOrder, n);
   if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(ZF_ERR_ARG, "bad hist buffer");
   if (n > 46000) return fail(ZF_ERR_ARG, "n = %d exceeds the supported maximum 46000", n);
-  if (o.z0 != 0 && o.z0 != 1) return fail(ZF_ERR_ARG, "unknown guess kind %d", o.z0);
+  if (o.z0 != ZF_Z0_GIVEN && o.z0 != ZF_Z0_SCALED_IDENTITY && o.z0 != ZF_Z0_LEARNED)
+    return fail(ZF_ERR_ARG, "unknown guess kind %d", o.z0);
+  if (o.z0 == ZF_Z0_GIVEN && !Z0) return fail(ZF_ERR_ARG, "opts.z0 = ZF_Z0_GIVEN needs a Z0");
 
   // arithmetic of the two phases (Table I): the first phase in the requested
   // precision; the refinement phase (Sec. IV.B) with an FP64 residual and a BF16x3
@@ -702,7 +784,7 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   const Arith hd = o.refine == ZF_REFINE_F32 ? AR_F32 : o.refine == ZF_REFINE_EMU ? AR_EMU : AR_F64;
   const Arith hc = (o.refine == ZF_REFINE_F64_DELTA || o.refine == ZF_REFINE_EMU) ? AR_X3 : hd;
   const bool high = refine && (hd == AR_F64 || hd == AR_EMU);  // FP64 master
-  const bool learned = !Z0 && o.z0 == 1;
+  const bool learned = !Z0 && o.z0 == ZF_Z0_LEARNED;
   const bool need_pairs = ar_pairs(la) || (refine && ar_pairs(hc));
   const bool need_f32 = la == AR_F32 || ar_f16(la) || (refine && hd == AR_F32);
   const bool use_h = fp64_only || high;
@@ -722,12 +804,14 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   c.sigma = 1.0;
   c.oz_slices = oz_slices_env();
   c.oz_s_ready = false;
+  c.log = log;
   const int s_fmt = ar_f16(la) ? 2 : 1;  // split format of S: FP16 or BF16 halves
   series(o.order, c.c);
   const int max_l = o.max_sweeps > 0 ? o.max_sweeps : 100;
   const int max_h = o.max_refine > 0 ? o.max_refine : 10;
 
   // setup: operands of S, then Z0
+  TraceRange setup_range("zf.setup");
   HIP_TRY(launch_split_pad(S, n, n, np, s_pairs ? w->s_hi : nullptr, s_pairs ? w->s_lo : nullptr,
                            (use_h || learned) ? w->s64 : nullptr,
                            need_f32 ? w->s32 : nullptr, false, s_fmt, st));
@@ -758,6 +842,7 @@ static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& 
   if (ar_f16(la))  // the initializers write BF16 pairs; the FP16 halves replace them
     HIP_TRY(launch_widen(w->z32[0], np, nullptr, nullptr, st, nullptr, w->zr_hi[0], w->zr_lo[0],
                          w->zc_hi[0], w->zc_lo[0], 1.0f, PAIR_F16));
+  setup_range.end();
 
   std::vector<double> h;
   int cur = 0;
@@ -821,6 +906,28 @@ done:
   return flags;
 }
 
+// refine_core under a roctx range, with one ZF_LOG line for the call's result.
+static int refine_impl(const double* S, const double* Z0, int n, const zf_opts& o, double* Z,
+                       zf_result* res, double* hist, int hist_cap, hipStream_t st) {
+  TraceRange range("zf_refine");
+  const bool log = log_on();
+  zf_result r;
+  memset(&r, 0, sizeof r);
+  const auto t0 = std::chrono::steady_clock::now();
+  const int rc = refine_core(S, Z0, n, o, Z, &r, hist, hist_cap, st, log);
+  if (res) *res = r;
+  if (log) {
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    log_line("\"event\": \"refine\", \"n\": %d, \"order\": %d, \"precision\": %d, \"refine\": %d, "
+             "\"stop\": %d, \"rc\": %d, \"iters\": %d, \"low_evals\": %d, \"high_evals\": %d, "
+             "\"final_rms\": %.6e, \"z0_used\": %d, \"flags\": %d, \"ms\": %.3f",
+             n, o.order, o.precision, o.refine, o.stop, rc, r.iters, r.low_evals, r.high_evals,
+             r.final_rms, r.z0_used, r.flags, ms);
+  }
+  return rc;
+}
+
 }  // namespace zf
 
 using namespace zf;
@@ -835,7 +942,7 @@ void zf_default_opts(zf_opts* o) {
   o->max_sweeps = 100;
   o->refine = ZF_REFINE_F64_DELTA;
   o->max_refine = 10;
-  o->z0 = 0;
+  o->z0 = ZF_Z0_SCALED_IDENTITY;
 }
 
 int zf_refine_ex(const double* S, const double* Z0, int n, const zf_opts* opts, double* Z,
@@ -860,8 +967,8 @@ int zf_refine(const double* S, const double* Z0, int n, int order, int precision
   return rc;
 }
 
-int zf_residual(const double* S, const double* Z, int n, double* err_f, void* stream) {
-  if (!S || !Z || !err_f) return fail(ZF_ERR_ARG, "NULL argument");
+int zf_residual(const double* S, const double* Z, int n, double* rms, void* stream) {
+  if (!S || !Z || !rms) return fail(ZF_ERR_ARG, "NULL argument");
   if (n <= 0) return fail(ZF_ERR_ARG, "n must be >= 1 (got %d)", n);
   hipStream_t st = (hipStream_t)stream;
   const int np = pad_order(n);
@@ -881,7 +988,7 @@ int zf_residual(const double* S, const double* Z, int n, double* err_f, void* st
   double e = 0.0;
   ZF_TRY(delta_eval(c, AR_F64, AR_F64, 0, &e));
   if (g_prof.on) prof_harvest();
-  *err_f = e;
+  *rms = e / sqrt((double)n);
   g_err.clear();
   return 0;
 }
@@ -968,7 +1075,7 @@ void zf_release(void) {
 
 const char* zf_last_error(void) { return g_err.c_str(); }
 
-int zf_version(void) { return 3; }
+int zf_version(void) { return 4; }
 
 // ---- per-kernel timing ------------------------------------------------------
 void zf_profile_enable(int on) { g_prof.on = on != 0; }
@@ -1006,29 +1113,6 @@ int zf_features(const double* S, int n, float* feats, void* stream) {
   HIP_TRY(hipStreamSynchronize(st));
   g_err.clear();
   return 0;
-}
-
-// 3x3 solve by Gaussian elimination with partial pivoting
-static bool solve3(double A[3][3], double b[3], double x[3]) {
-  int p[3] = {0, 1, 2};
-  for (int k = 0; k < 3; ++k) {
-    int piv = k;
-    for (int i = k + 1; i < 3; ++i)
-      if (fabs(A[p[i]][k]) > fabs(A[p[piv]][k])) piv = i;
-    std::swap(p[k], p[piv]);
-    if (A[p[k]][k] == 0.0) return false;
-    for (int i = k + 1; i < 3; ++i) {
-      const double f = A[p[i]][k] / A[p[k]][k];
-      for (int j = k; j < 3; ++j) A[p[i]][j] -= f * A[p[k]][j];
-      b[p[i]] -= f * b[p[k]];
-    }
-  }
-  for (int k = 2; k >= 0; --k) {
-    double s = b[p[k]];
-    for (int j = k + 1; j < 3; ++j) s -= A[p[k]][j] * x[j];
-    x[k] = s / A[p[k]][k];
-  }
-  return true;
 }
 
 int zf_guess_label(const double* S, const double* Z, int n, double* c, void* stream) {

@@ -189,6 +189,24 @@ hipError_t launch_unpad_f32(const float* src, int np, int n, double* dst, hipStr
 hipError_t launch_norm_finalize(const double* partials, int count, double* out, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
+// Tracing (zf_api.hip).
+// ZF_LOG=1 writes one JSON object per line to stderr for every call, residual
+// evaluation and result; ZF_LOG=<path> appends the same lines to that file.
+// log_on() reads the variable (once per API call is enough); log_line formats one
+// line (the caller passes the JSON body without braces) and flushes it.
+bool log_on();
+void log_line(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+// roctx ranges around the stages of a call (rocprofv3 --marker-trace shows them;
+// without a profiler attached they cost a function call).
+struct TraceRange {
+  explicit TraceRange(const char* name);
+  ~TraceRange() { end(); }
+  void end();  // close the range before the scope ends (idempotent)
+  bool live = true;
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
 // Error reporting shared by the translation units (zf_api.hip): set the thread's
 // message and return code; clear_error() empties it.
 int set_error(int code, const char* fmt, ...);

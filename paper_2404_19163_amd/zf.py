@@ -28,6 +28,7 @@ ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NONFINITE, ERR_NOT_CONVERGED = -1, -2, -3, -4, 
 _PREC = {"fp64": FP64, "bf16x3": BF16X3, "fp16x3": FP16X3, "bf16": BF16, "fp32": FP32,
          "fp16": FP16}
 _STOP = {"ratio": STOP_RATIO, "monotone": STOP_MONOTONE}
+_GUESS = {"identity": Z0_SCALED_IDENTITY, "learned": Z0_LEARNED, "given": Z0_GIVEN}
 _REFINE = {"off": REFINE_OFF, "f64_delta": REFINE_F64_DELTA, "f64_full": REFINE_F64_FULL,
            "f32": REFINE_F32, "emu": REFINE_EMU}
 KERNEL_CLASSES = ("gemm_x3", "gemm_x3_sym", "gemm_f64", "gemm_f64_sym", "gemm_hh", "gemm_hh_sym",
@@ -195,7 +196,7 @@ def refine(S: torch.Tensor, Z0: torch.Tensor | None = None, *, order: int = 2,
         out = torch.empty_like(S)
     z_ptr = _dev(out, "out", n)
     o = Opts(order, _PREC[precision], _STOP[stop], max_sweeps, _REFINE[refine], max_refine,
-             1 if guess == "learned" else 0)
+             _GUESS[guess])
     r = Result()
     hist = (ctypes.c_double * max(hist_cap, 1))()
     rc = lib().zf_refine_ex(s_ptr, z0_ptr, n, ctypes.byref(o), z_ptr, ctypes.byref(r), hist,
@@ -233,7 +234,7 @@ def refine_batched(S_list, Z0_list=None, *, order: int = 2, precision: str = "bf
     zp = (ctypes.c_void_p * count)(*[_dev(Z, "out", n) for Z, n in zip(out, ns)])
     narr = (ctypes.c_int * count)(*ns)
     o = Opts(order, _PREC[precision], _STOP[stop], max_sweeps, _REFINE[refine], max_refine,
-             1 if guess == "learned" else 0)
+             _GUESS[guess])
     res = (Result * count)()
     hist = (ctypes.c_double * max(count * hist_cap, 1))()
     rc = lib().zf_refine_batched(count, sp, z0p, narr, ctypes.byref(o), zp, res, hist, hist_cap,
@@ -278,6 +279,11 @@ def batched_use_graph(on: bool = True) -> None:
     lib().zf_batched_use_graph(1 if on else 0)
 
 
+def batched_release() -> None:
+    """Free the batched path's cached arena and graph (zf_batched_release)."""
+    lib().zf_batched_release()
+
+
 def refine_basic(S, Z0, order, precision, out, hist_cap=256, stream=None):
     """The short form zf_refine(S, Z0, n, order, precision) -> (rc, iters, hist)."""
     n = S.shape[0]
@@ -293,7 +299,7 @@ def refine_basic(S, Z0, order, precision, out, hist_cap=256, stream=None):
 
 
 def residual(S: torch.Tensor, Z: torch.Tensor, stream=None) -> float:
-    """||Z^T S Z - I||_F with FP64 products (zf_residual)."""
+    """||Z^T S Z - I||_F / sqrt(n) with FP64 products (zf_residual)."""
     n = S.shape[0]
     v = ctypes.c_double(0.0)
     _check(lib().zf_residual(_dev(S, "S", n), _dev(Z, "Z", n), n, ctypes.byref(v), _stream(stream)))

@@ -57,6 +57,7 @@ def test_version_and_default_opts(libzf):
     o = zf.Opts()
     L.zf_default_opts(ctypes.byref(o))
     assert (o.order, o.precision, o.stop, o.max_sweeps, o.refine, o.max_refine) == (2, 1, 0, 100, 1, 10)
+    assert o.z0 == zf.Z0_SCALED_IDENTITY  # opts.z0 takes the values of enum zf_z0_kind
     assert L.zf_last_error() == b""
 
 

@@ -124,7 +124,7 @@ def test_refine_emulated_slice_override(zf, monkeypatch):
 
 def test_refine_emulated_rejects_large_n(zf):
     S = _cuda(np.eye(4))
-    o = zf.Opts(2, zf.BF16X3, zf.STOP_RATIO, 100, zf.REFINE_EMU, 10, 0)
+    o = zf.Opts(2, zf.BF16X3, zf.STOP_RATIO, 100, zf.REFINE_EMU, 10, zf.Z0_SCALED_IDENTITY)
     res = zf.Result()
     rc = zf.lib().zf_refine_ex(S.data_ptr(), None, 16385, ctypes.byref(o), S.data_ptr(),
                                ctypes.byref(res), None, 0, None)

@@ -184,8 +184,8 @@ def test_diagonal_S(zf):
 def test_residual_entry_point(zf):
     S = _S(300, 10)
     Z = O.lowdin(S) + 1e-3 * inputs.uniform_noise(300, 2)
-    e = zf.residual(_cuda(S), _cuda(Z))
-    assert e == pytest.approx(O.residual(S, Z), rel=1e-10)
+    rms = zf.residual(_cuda(S), _cuda(Z))
+    assert rms == pytest.approx(O.residual_rms(S, Z), rel=1e-10)
 
 
 def test_deterministic(zf):

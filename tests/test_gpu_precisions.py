@@ -144,13 +144,13 @@ def test_fp16_learned_and_refinement_modes(zf):
 def test_unknown_modes_rejected(zf):
     S = _cuda(_S(64, 0))
     import ctypes
-    o = zf.Opts(2, 9, zf.STOP_RATIO, 100, 1, 10, 0)          # precision 9 does not exist
+    o = zf.Opts(2, 9, zf.STOP_RATIO, 100, 1, 10, 1)          # precision 9 does not exist
     res = zf.Result()
     Z = torch.empty_like(S)
     rc = zf.lib().zf_refine_ex(S.data_ptr(), None, 64, ctypes.byref(o), Z.data_ptr(),
                                ctypes.byref(res), None, 0, None)
     assert rc == zf.ERR_ARG
-    o = zf.Opts(2, zf.FP32, zf.STOP_RATIO, 100, 7, 10, 0)   # refine mode 7 does not exist
+    o = zf.Opts(2, zf.FP32, zf.STOP_RATIO, 100, 7, 10, 1)   # refine mode 7 does not exist
     res = zf.Result()
     Z = torch.empty_like(S)
     rc = zf.lib().zf_refine_ex(S.data_ptr(), None, 64, ctypes.byref(o), Z.data_ptr(),

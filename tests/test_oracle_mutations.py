@@ -5,8 +5,10 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
+from oracle import zf_guess_oracle as G
 from oracle import zf_oracle as O
 from tests import test_oracle_coeffs as TC
+from tests import test_oracle_pins as TP
 from tests import test_oracle_congruence as TH
 from tests import test_oracle_ozaki as TZ
 from tests import test_oracle_recursion as TR
@@ -68,6 +70,36 @@ def _nonstrict_stop(it, err, prev, order, rule):
     return err >= prev ** (order + 1)
 
 
+def _frobenius_bound(S):
+    return float(np.linalg.norm(S))
+
+
+def _max_entry_bound(S):
+    return float(S.shape[0] * np.max(np.abs(S)))
+
+
+def _gershgorin_diag_twice(S):
+    r = np.sum(np.abs(S), axis=1)
+    d = np.diag(S)
+    return float(np.max(r)), float(np.min(d - r)), float(np.mean(r))
+
+
+def _rms_over_n(S, Z):
+    return O.residual(S, Z) / S.shape[0]
+
+
+def _guess_elementwise_square(S, c):
+    g, _, _ = G.gershgorin(S)
+    St = S / g
+    return (c[0] * np.eye(S.shape[0]) + c[1] * St + c[2] * St * St) / np.sqrt(g)
+
+
+def _guess_dropped_linear(S, c):
+    g, _, _ = G.gershgorin(S)
+    St = S / g
+    return (c[0] * np.eye(S.shape[0]) + c[2] * St @ St) / np.sqrt(g)
+
+
 MUTANTS = [
     ("delta_coefficients", _dropped_term, lambda g: TR.test_spectral_map_history()),
     ("delta_coefficients", _dropped_term, lambda g: TC.test_x_form_coefficients_match_appendix_a(g)),
@@ -79,11 +111,32 @@ MUTANTS = [
     ("ozaki_product", _ozaki_shifted, lambda g: TZ.test_integer_matrices_are_exact()),
     ("split", _truncating_split, lambda g: TS.test_bf16_rounding_edge_values()),
     ("stop_now", _nonstrict_stop, lambda g: TC.test_stop_rule_algorithm_2()),
+    ("gershgorin_max_row_sum", _frobenius_bound, lambda g: TP.test_gershgorin_hand_matrix()),
+    ("gershgorin_max_row_sum", _frobenius_bound, lambda g: TP.test_scaled_identity_hand_matrix()),
+    ("gershgorin_max_row_sum", _max_entry_bound, lambda g: TP.test_scaled_identity_hand_matrix()),
+    ("residual_rms", _rms_over_n, lambda g: TP.test_residual_rms_closed_form(0.19)),
+    ("residual_rms", _rms_over_n, lambda g: TP.test_residual_rms_larger_order()),
+]
+
+# mistakes planted in the learned guess's oracle
+GUESS_MUTANTS = [
+    ("gershgorin", _gershgorin_diag_twice, lambda g: TP.test_gershgorin_hand_matrix()),
+    ("gershgorin", _gershgorin_diag_twice, lambda g: TP.test_features_hand_matrix()),
+    ("guess_matrix", _guess_elementwise_square, lambda g: TP.test_guess_matrix_spectral()),
+    ("guess_matrix", _guess_dropped_linear, lambda g: TP.test_guess_matrix_spectral()),
 ]
 
 
 @pytest.mark.parametrize("name,mutant,pin", MUTANTS, ids=[f"{m[0]}-{i}" for i, m in enumerate(MUTANTS)])
 def test_pin_catches_mutant(monkeypatch, golden_dir, name, mutant, pin):
     monkeypatch.setattr(O, name, mutant)
+    with pytest.raises(AssertionError):
+        pin(golden_dir)
+
+
+@pytest.mark.parametrize("name,mutant,pin", GUESS_MUTANTS,
+                         ids=[f"{m[0]}-{i}" for i, m in enumerate(GUESS_MUTANTS)])
+def test_guess_pin_catches_mutant(monkeypatch, golden_dir, name, mutant, pin):
+    monkeypatch.setattr(G, name, mutant)
     with pytest.raises(AssertionError):
         pin(golden_dir)
