@@ -8,13 +8,20 @@ the timed region starts.
 
 Reported (one JSON line):
   value        refined-Z TFLOP/s of the mixed path (BF16x3 sweeps + FP64
-               refinement): algorithmic flops / time, where one residual
-               evaluation counts 4 N^3 (S Z and Z^T (S Z)) and one update of
-               order m counts 2 m N^3 (delta^k products and Z Q)
+               refinement) on the N = 4096 overlap: the method's irreducible
+               flops / time, where one residual evaluation counts 3 N^3 (S Z and
+               the symmetric Z^T (S Z)) and one update of order m counts
+               (m + 1) N^3 (m - 1 symmetric delta products and Z Q);
+               tflops_paper_count gives the dense count (4 N^3 + 2 m N^3)
   ms_per_step  its time-to-solution; fp64.* holds the plain FP64 path
   roofline     the dominant kernel (most time in the timed region), timed with
-               HIP events on the library's stream
-  cpu_baseline the CPU FP64 oracle on a bounded sample of the same workload
+               HIP events on the library's stream, and every BF16 kernel together
+  cpu_baseline the CPU FP64 oracle on the same matrix (one evaluation and one
+               update, all threads and one thread), extrapolated to the solve:
+               T_oracle / T_gpu
+  configs      the other workloads (N = 256 FP64, the N = 5049 cluster, the
+               N = 3000 MD warm start, the 512-matrix batch), each with its
+               oracle-checked residual (--headline-only skips them)
 """
 import argparse
 import json
@@ -22,6 +29,8 @@ import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -75,6 +84,16 @@ WORKLOADS = {
 
 
 def alg_flops(n: int, order: int, evals: int, updates: int) -> float:
+    """The method's irreducible flops: a residual evaluation is S Z (2 N^3) plus the
+    symmetric Z^T (S Z) (N^3); an update of order m is m - 1 symmetric delta products
+    plus Z Q (2 N^3).  Order 2: 6 N^3 per sweep."""
+    n3 = float(n) ** 3
+    return n3 * (3.0 * evals + (order + 1.0) * updates)
+
+
+def paper_flops(n: int, order: int, evals: int, updates: int) -> float:
+    """The paper's count of the same work with every product dense (Sec. III.B: the
+    four N x N products of a sweep): 4 N^3 per evaluation, 2 m N^3 per update."""
     return float(n) ** 3 * (4.0 * evals + 2.0 * order * updates)
 
 
@@ -86,7 +105,199 @@ def kernel_alg_flops(cls: str, n: int) -> float:
             "gemm_hh": 2 * n ** 3, "gemm_hh_sym": n * n * (n + 1),
             "gemm_f32": 2 * n ** 3, "gemm_f32_sym": n * n * (n + 1),
             "gemm_x3f16": 6 * n ** 3, "gemm_x3f16_sym": 3 * n * n * (n + 1),
-            "gemm_hhf16": 2 * n ** 3, "gemm_hhf16_sym": n * n * (n + 1)}[cls]
+            "gemm_hhf16": 2 * n ** 3, "gemm_hhf16_sym": n * n * (n + 1)}.get(cls, 0.0)
+
+
+def timed_solves(fn, steps: int, warmup: int):
+    """Median-free mean wall time per call of fn() over `steps` calls after `warmup`
+    untimed ones, bracketed by device synchronizations; returns (seconds, last result)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(steps):
+        last = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, last
+
+
+def lowdin_error(S_np, Z_list):
+    """Relative Frobenius distance of each Z to the Loewdin factor S^(-1/2) (dense
+    eigendecomposition, the closed form every polynomial-in-S guess converges to)."""
+    from oracle import zf_oracle as O
+    L = O.lowdin(S_np)
+    nl = float(np.linalg.norm(L))
+    return [float(np.linalg.norm(Z - L) / nl) for Z in Z_list]
+
+
+def cpu_oracle_baseline(S_np, order: int, evals: int, updates: int, gpu_s: float,
+                        workload: str):
+    """The CPU FP64 oracle on the same matrix: one residual evaluation and one update of
+    its recursion with every BLAS thread the process may use, and one evaluation on a
+    single thread.  The solve's oracle time is extrapolated from these to the FP64
+    path's evaluation and update counts; T_oracle / T_gpu is a time ratio of the same
+    solve."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import zf_oracle as O
+    n = S_np.shape[0]
+    eye = np.eye(n)
+    Z = O.scaled_identity_guess(S_np)
+
+    def one_eval(Z):
+        delta = eye - O.gram(S_np, Z)
+        return delta, O.frobenius(delta)
+
+    t0 = time.perf_counter()
+    delta, _ = one_eval(Z)
+    t_eval = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Z = Z + Z @ O.correction(delta, order)
+    t_upd = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        one_eval(Z)
+        t_eval1 = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    est = t_eval * evals + t_upd * updates
+    flops = alg_flops(n, order, 1, 1)
+    try:
+        blas = np.show_config(mode="dicts")["Build Dependencies"]["blas"]["name"]
+    except Exception:  # noqa: BLE001 (older numpy: no dict mode)
+        blas = "unknown"
+    return {"value": round(flops / (t_eval + t_upd) / 1e12, 5), "unit": "TFLOP/s",
+            "cores": len(os.sched_getaffinity(0)), "threads": threads, "kind": "oracle",
+            "blas": blas,
+            "sample": f"{workload}: one residual evaluation ({t_eval:.2f} s) and one update "
+                      f"({t_upd:.2f} s) of the FP64 oracle recursion, irreducible-flop basis",
+            "eval_s": round(t_eval, 3), "update_s": round(t_upd, 3),
+            "eval_s_1thread": round(t_eval1, 3),
+            "solve_s_est": round(est, 2),
+            "solve_s_est_1thread": round(est * t_eval1 / t_eval, 1),
+            "solve_counts": {"evals": evals, "updates": updates},
+            "time_ratio_vs_gpu": round(est / gpu_s, 1),
+            "time_ratio_vs_gpu_1thread": round(est * t_eval1 / t_eval / gpu_s, 1)}
+
+
+def run_single(args, name: str, S_np, with_profile: bool, legs=("fp64", "emu")) -> dict:
+    """Mixed (headline) and FP64 legs of zf_refine on one matrix, with per-kernel
+    times, roofline fractions and oracle checks."""
+    import torch
+
+    from oracle import zf_oracle as O
+    from paper_2404_19163_amd import zf
+
+    n = S_np.shape[0]
+    dev = torch.device("cuda:0")
+    S = torch.from_numpy(S_np).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def run(precision, out, refine="f64_delta"):
+        return zf.refine(S, None, order=args.order, precision=precision, out=out, stream=stream,
+                         refine=refine)
+
+    Zm = torch.empty_like(S)
+    for _ in range(args.warmup):
+        run("bf16x3", Zm)
+    torch.cuda.synchronize()
+    if with_profile:
+        zf.profile_reset()
+        zf.profile_enable(True)
+    mixed_s, last = timed_solves(lambda: run("bf16x3", Zm), args.steps, 0)
+    prof = {}
+    if with_profile:
+        zf.profile_enable(False)
+        prof = zf.profile_read()
+    print(f"[bench] {name} mixed: {mixed_s * 1e3:.3f} ms/step iters={last.iters} "
+          f"evals={last.low_evals}+{last.high_evals} rms={last.final_rms:.3e}", file=sys.stderr,
+          flush=True)
+    # the same steps without the per-GEMM event pairs
+    noev_s, _ = timed_solves(lambda: run("bf16x3", Zm), args.steps, 0) if with_profile else (mixed_s, None)
+    evals = last.low_evals + last.high_evals
+    updates = (last.low_evals - 1) + max(last.high_evals - 1, 0)
+    out = {"ms": round(mixed_s * 1e3, 4), "ms_without_events": round(noev_s * 1e3, 4),
+           "iters": last.iters, "low_evals": last.low_evals, "high_evals": last.high_evals,
+           "final_rms": last.final_rms,
+           "tflops": round(alg_flops(n, args.order, evals, updates) / mixed_s / 1e12, 3),
+           "tflops_paper_count": round(paper_flops(n, args.order, evals, updates) / mixed_s / 1e12, 3)}
+    res = {"n": n, "mixed": out, "prof": prof, "steps_timed": args.steps}
+
+    if "fp64" in legs and args.fp64_steps > 0:
+        Zd = torch.empty_like(S)
+        fp64_s, r64 = timed_solves(lambda: run("fp64", Zd), args.fp64_steps, 1)
+        updates64 = r64.high_evals - 1
+        res["fp64"] = {"ms": round(fp64_s * 1e3, 3),
+                       "tflops": round(alg_flops(n, args.order, r64.high_evals, updates64) / fp64_s / 1e12, 3),
+                       "tflops_paper_count": round(paper_flops(n, args.order, r64.high_evals, updates64) / fp64_s / 1e12, 3),
+                       "iters": r64.iters, "evals": r64.high_evals, "final_rms": r64.final_rms}
+        res["Zd"] = Zd
+        print(f"[bench] {name} fp64: {fp64_s * 1e3:.3f} ms/step iters={r64.iters} "
+              f"rms={r64.final_rms:.3e}", file=sys.stderr, flush=True)
+    if "emu" in legs and args.fp64_steps > 0 and n <= 16384:
+        Ze = torch.empty_like(S)
+        emu_s, re_ = timed_solves(lambda: run("bf16x3", Ze, "emu"), args.fp64_steps, 1)
+        res["emu"] = {"ms": round(emu_s * 1e3, 3), "evals": [re_.low_evals, re_.high_evals],
+                      "final_rms": re_.final_rms,
+                      "slices": int(os.environ.get("ZF_EMU_SLICES", "7")),
+                      "fp64_rms": zf.residual(S, Ze)}
+        print(f"[bench] {name} mixed, emulated FP64 residual: {emu_s * 1e3:.3f} ms/step "
+              f"rms={re_.final_rms:.3e}", file=sys.stderr, flush=True)
+
+    # residuals and distances checked by the CPU oracle
+    Zm_np = Zm.cpu().numpy()
+    checks = {"oracle_rms_mixed": O.residual_rms(S_np, Zm_np)}
+    Zs = [Zm_np]
+    if "Zd" in res:
+        Zd_np = res.pop("Zd").cpu().numpy()
+        checks["oracle_rms_fp64"] = O.residual_rms(S_np, Zd_np)
+        checks["rel_diff_mixed_vs_fp64"] = float(np.linalg.norm(Zm_np - Zd_np) / np.linalg.norm(Zd_np))
+        Zs.append(Zd_np)
+    if not args.no_lowdin:
+        t0 = time.perf_counter()
+        errs = lowdin_error(S_np, Zs)
+        checks["lowdin_rel_err_mixed"] = errs[0]
+        if len(errs) > 1:
+            checks["lowdin_rel_err_fp64"] = errs[1]
+        checks["lowdin_eigh_s"] = round(time.perf_counter() - t0, 2)
+    res["checks"] = checks
+    return res
+
+
+def kernel_table(prof: dict, n: int, total_s: float) -> dict:
+    return {k: {"launches": v[0], "total_ms": round(v[1], 4),
+                "avg_us": round(v[1] / max(v[0], 1) * 1e3, 2),
+                "share": round(v[1] / max(total_s * 1e3, 1e-9), 4),
+                "alg_tflops": round(kernel_alg_flops(k, n) / (v[1] / 1e3 / v[0]) / 1e12, 2),
+                "exec_tflops": round(v[2] / (v[1] / 1e3) / 1e12, 2)}
+            for k, v in prof.items() if v[0]}
+
+
+def roofline(prof: dict, n: int, total_s: float) -> dict:
+    """Dominant kernel (most time) against its dtype's peak, plus the time-weighted
+    fraction of all BF16 kernels together (algorithmic and executed MFMA flops over
+    their summed time) and the whole call's matrix-core fraction."""
+    dom = max(prof, key=lambda k: prof[k][1])
+    launches, tot_ms, _ = prof[dom]
+    avg_s = tot_ms / 1e3 / max(launches, 1)
+    ach = kernel_alg_flops(dom, n) / avg_s / 1e12
+    peak = PEAK_TFLOPS[KCLASS_DTYPE[dom]]
+    bf = {k: v for k, v in prof.items() if v[0] and KCLASS_DTYPE.get(k) == "bf16"}
+    bf_s = sum(v[1] for v in bf.values()) / 1e3
+    bf_alg = sum(kernel_alg_flops(k, n) * v[0] for k, v in bf.items())
+    bf_exec = sum(v[2] for v in bf.values())
+    mfma_s = sum(v[2] / (PEAK_TFLOPS[KCLASS_DTYPE[k]] * 1e12) for k, v in prof.items() if v[0])
+    traffic, alg_bytes = measured_traffic(dom, n)
+    return {"bound": "mfma", "kernel": dom, "achieved": round(ach, 2), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated)",
+            "alg_bytes": alg_bytes,
+            "bf16_kernels_frac": round(bf_alg / bf_s / 1e12 / PEAK_TFLOPS["bf16"], 4) if bf_s else None,
+            "bf16_kernels_exec_frac": round(bf_exec / bf_s / 1e12 / PEAK_TFLOPS["bf16"], 4) if bf_s else None,
+            "bf16_kernels_share_of_call": round(bf_s / total_s, 4),
+            "whole_call_frac": round(mfma_s / total_s, 4)}
 
 
 def main() -> int:
@@ -98,10 +309,16 @@ def main() -> int:
                     choices=sorted(WORKLOADS) + ["batched512", "md3000", "table1", "congruence"])
     ap.add_argument("--n", type=int, default=4096, help="order of the table1 workload")
     ap.add_argument("--frames", type=int, default=64, help="frames of the md3000 workload")
+    ap.add_argument("--graph-sweeps", type=int, default=None,
+                    help="macro-sweeps per graph launch of the batched workload (0: all)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--order", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lowdin", action="store_true",
+                    help="skip the dense-eigendecomposition distance checks")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the N=4096 workload (skip the other configurations)")
     ap.add_argument("--mixed-only", action="store_true", help="skip the FP64 path (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
@@ -120,161 +337,57 @@ def main() -> int:
               "the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         return 2
 
-    import numpy as np
-    import torch
-
-    from paper_2404_19163_amd import inputs, zf
+    from paper_2404_19163_amd import inputs
 
     if args.workload == "batched512":
-        return bench_batched(args)
+        print(json.dumps(bench_batched(args)), flush=True)
+        return 0
     if args.workload == "md3000":
-        return bench_md(args)
+        print(json.dumps(bench_md(args)), flush=True)
+        return 0
     if args.workload == "table1":
         return bench_table1(args)
     if args.workload == "congruence":
         return bench_congruence(args)
+    if args.mixed_only:
+        args.fp64_steps = 0
     wl = WORKLOADS[args.workload]
-    n = wl["n"]
     t0 = time.perf_counter()
     S_np = inputs.workload(args.workload, args.seed)
-    gen_s = time.perf_counter() - t0
-    print(f"[bench] generated {args.workload} N={n} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    n = S_np.shape[0]
+    print(f"[bench] generated {args.workload} N={n} in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
 
-    dev = torch.device("cuda:0")
-    S = torch.from_numpy(S_np).to(dev)
-    stream = torch.cuda.current_stream()
+    r = run_single(args, args.workload, S_np, with_profile=True)
+    mixed = r["mixed"]
+    mixed_s = mixed["ms"] / 1e3
+    total_s = mixed_s * r["steps_timed"]
+    prof = r["prof"]
+    fp64 = r.get("fp64")
 
-    def run(precision, out):
-        return zf.refine(S, None, order=args.order, precision=precision, out=out, stream=stream,
-                         refine="f64_delta")
-
-    # ---- mixed path (the headline) --------------------------------------
-    Zm = torch.empty_like(S)
-    for _ in range(args.warmup):
-        run("bf16x3", Zm)
-    torch.cuda.synchronize()
-    zf.profile_reset()
-    zf.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    last = None
-    for _ in range(args.steps):
-        last = run("bf16x3", Zm)
-    torch.cuda.synchronize()
-    mixed_s = (time.perf_counter() - t0) / args.steps
-    zf.profile_enable(False)
-    prof = zf.profile_read()
-    print(f"[bench] mixed: {mixed_s * 1e3:.3f} ms/step iters={last.iters} "
-          f"evals={last.low_evals}+{last.high_evals} rms={last.final_rms:.3e}", file=sys.stderr,
-          flush=True)
-
-    # the same steps without the per-GEMM event pairs (they cost a few µs per launch,
-    # which shows at small N)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        run("bf16x3", Zm)
-    torch.cuda.synchronize()
-    mixed_noev_s = (time.perf_counter() - t0) / args.steps
-
-    mixed_flops = alg_flops(n, args.order, last.low_evals + last.high_evals,
-                            (last.low_evals - 1) + max(last.high_evals - 1, 0))
-    value = mixed_flops / mixed_s / 1e12
-
-    # dominant kernel of the timed region
-    dom = max(prof, key=lambda k: prof[k][1])
-    launches, tot_ms, exec_flops = prof[dom]
-    avg_s = tot_ms / 1e3 / max(launches, 1)
-    ach = kernel_alg_flops(dom, n) / avg_s / 1e12
-    peak = PEAK_TFLOPS[KCLASS_DTYPE[dom]]
-    # whole-call matrix-core fraction: sum over kernel classes of executed MFMA flops
-    # over that class's peak, divided by the measured time of the timed steps
-    mfma_s = sum(v[2] / (PEAK_TFLOPS[KCLASS_DTYPE[k]] * 1e12) for k, v in prof.items() if v[0])
-    whole_frac = mfma_s / (mixed_s * args.steps)
-    kernels = {k: {"launches": v[0], "total_ms": round(v[1], 4),
-                   "avg_us": round(v[1] / max(v[0], 1) * 1e3, 2),
-                   "share": round(v[1] / max(mixed_s * 1e3 * args.steps, 1e-9), 4),
-                   "alg_tflops": round(kernel_alg_flops(k, n) / (v[1] / 1e3 / v[0]) / 1e12, 2)
-                   if v[0] else None}
-               for k, v in prof.items() if v[0]}
-
-    # ---- FP64 path -------------------------------------------------------
-    fp64 = None
-    if not args.mixed_only and args.fp64_steps > 0:
-        Zd = torch.empty_like(S)
-        run("fp64", Zd)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r64 = None
-        for _ in range(args.fp64_steps):
-            r64 = run("fp64", Zd)
-        torch.cuda.synchronize()
-        fp64_s = (time.perf_counter() - t0) / args.fp64_steps
-        f64_flops = alg_flops(n, args.order, r64.high_evals, r64.high_evals - 1)
-        fp64 = {"ms": round(fp64_s * 1e3, 3), "tflops": round(f64_flops / fp64_s / 1e12, 3),
-                "iters": r64.iters, "final_rms": r64.final_rms}
-        print(f"[bench] fp64: {fp64_s * 1e3:.3f} ms/step iters={r64.iters} rms={r64.final_rms:.3e}",
-              file=sys.stderr, flush=True)
-
-    # ---- mixed path with the emulated FP64 residual (int8 matrix cores) ----
-    emu = None
-    if not args.mixed_only and args.fp64_steps > 0 and n <= 16384:
-        Ze = torch.empty_like(S)
-        zf.refine(S, None, order=args.order, precision="bf16x3", out=Ze, stream=stream,
-                  refine="emu")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        re_ = None
-        for _ in range(args.fp64_steps):
-            re_ = zf.refine(S, None, order=args.order, precision="bf16x3", out=Ze, stream=stream,
-                            refine="emu")
-        torch.cuda.synchronize()
-        emu_s = (time.perf_counter() - t0) / args.fp64_steps
-        emu = {"ms": round(emu_s * 1e3, 3), "evals": [re_.low_evals, re_.high_evals],
-               "final_rms": re_.final_rms, "slices": int(os.environ.get("ZF_EMU_SLICES", "7")),
-               "fp64_rms": zf.residual(S, Ze)}
-        print(f"[bench] mixed, emulated FP64 residual: {emu_s * 1e3:.3f} ms/step "
-              f"rms={re_.final_rms:.3e}", file=sys.stderr, flush=True)
-
-    # ---- residuals checked by the CPU oracle ----------------------------
-    from oracle import zf_oracle as O
-    Zm_np = Zm.cpu().numpy()
-    oracle_rms_mixed = O.residual_rms(S_np, Zm_np)
-    checks = {"oracle_rms_mixed": oracle_rms_mixed}
-    if fp64 is not None:
-        Zd_np = Zd.cpu().numpy()
-        checks["oracle_rms_fp64"] = O.residual_rms(S_np, Zd_np)
-        checks["rel_diff_mixed_vs_fp64"] = float(np.linalg.norm(Zm_np - Zd_np) / np.linalg.norm(Zd_np))
-
-    # ---- CPU baseline: the oracle on a bounded sample --------------------
     cpu = None
     if not args.no_cpu_baseline:
-        Z0 = O.scaled_identity_guess(S_np)
-        t0 = time.perf_counter()
-        res = O.refine(S_np, Z0, order=args.order, rule="none", max_sweeps=1)
-        cpu_s = time.perf_counter() - t0
-        cf = alg_flops(n, args.order, len(res.hist), len(res.hist) - 1)
-        cores = len(os.sched_getaffinity(0))
-        try:
-            blas = np.show_config(mode="dicts")["Build Dependencies"]["blas"]["name"]
-        except Exception:  # noqa: BLE001 (older numpy: no dict mode)
-            blas = "unknown"
-        cpu = {"value": round(cf / cpu_s / 1e12, 5), "unit": "TFLOP/s", "cores": cores,
-               "threads": torch.get_num_threads(), "kind": "oracle", "blas": blas,
-               "sample": f"{args.workload}: 2 FP64 residual evaluations + 1 update of the oracle "
-                         f"recursion ({cf:.3e} alg. flops) in {cpu_s:.2f} s"}
+        # the oracle runs the FP64 recursion: its counts are the FP64 path's (equal by
+        # the parity tests), else the mixed path's
+        ev = fp64["evals"] if fp64 else mixed["low_evals"] + mixed["high_evals"]
+        cpu = cpu_oracle_baseline(S_np, args.order, ev, ev - 1, mixed_s, args.workload)
+        if fp64:
+            cpu["time_ratio_vs_gpu_fp64_path"] = round(cpu["solve_s_est"] / (fp64["ms"] / 1e3), 1)
+        print(f"[bench] cpu oracle: eval {cpu['eval_s']} s, update {cpu['update_s']} s, "
+              f"1-thread eval {cpu['eval_s_1thread']} s", file=sys.stderr, flush=True)
 
-    if cpu is not None:
-        cpu["gpu_speedup"] = round(value / cpu["value"], 1)  # same algorithmic-flop rate basis
-    traffic, alg_bytes = measured_traffic(dom, n)
+    configs = {}
+    if not args.headline_only and args.workload == "gauss4096":
+        configs = other_configs(args)
+
     line = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": mixed["tflops"],
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(mixed_s * 1e3, 4),
+        "ms_per_step": mixed["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -283,28 +396,77 @@ def main() -> int:
         "config": {"workload": wl["desc"], "n": n, "seed": args.seed, "order": args.order,
                    "z0": "scaled identity", "stop": "ratio (Algorithm 2)",
                    "refine": "FP64 residual + BF16x3 correction"},
-        "time_to_solution_ms": round(mixed_s * 1e3, 4),
-        "ms_per_step_without_events": round(mixed_noev_s * 1e3, 4),
-        "iters": last.iters,
-        "low_evals": last.low_evals,
-        "high_evals": last.high_evals,
-        "final_rms": last.final_rms,
+        "flop_basis": "irreducible: 3 N^3 per residual evaluation (S Z and the symmetric "
+                      "Z^T (S Z)), (m + 1) N^3 per update (6 N^3 per order-2 sweep); "
+                      "tflops_paper_count uses 4 N^3 + 2 m N^3 (every product dense)",
+        "time_to_solution_ms": mixed["ms"],
+        "ms_per_step_without_events": mixed["ms_without_events"],
+        "tflops_paper_count": mixed["tflops_paper_count"],
+        "iters": mixed["iters"],
+        "low_evals": mixed["low_evals"],
+        "high_evals": mixed["high_evals"],
+        "final_rms": mixed["final_rms"],
         "fp64": fp64,
         # both legs timed without per-GEMM events
-        "speedup_vs_fp64": round(fp64["ms"] / (mixed_noev_s * 1e3), 3) if fp64 else None,
-        "mixed_emulated_residual": emu,
-        "checks": checks,
-        "kernels": kernels,
-        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(ach, 2), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic,
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                     "copy-calibrated)",
-                     "alg_bytes": alg_bytes,
-                     "whole_call_frac": round(whole_frac, 4)},
+        "speedup_vs_fp64": round(fp64["ms"] / mixed["ms_without_events"], 3) if fp64 else None,
+        "mixed_emulated_residual": r.get("emu"),
+        "checks": r["checks"],
+        "kernels": kernel_table(prof, n, total_s),
+        "roofline": roofline(prof, n, total_s),
         "cpu_baseline": cpu,
+        "configs": configs,
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def other_configs(args) -> dict:
+    """The remaining workloads in the same run, each reduced to its figures: N = 256
+    FP64 (the plain method), the N = 5049 cluster (mixed and FP64), the MD warm start at
+    N = 3000 and the 512-matrix batch.  Every result carries its oracle-checked RMS."""
+    import torch
+
+    from oracle import zf_oracle as O
+    from paper_2404_19163_amd import inputs, zf
+
+    out = {}
+    # plain method, N = 256, FP64, both stop rules
+    S_np = inputs.workload("gauss256", args.seed)
+    S = torch.from_numpy(S_np).to("cuda:0")
+    Z = torch.empty_like(S)
+    ref = O.refine(S_np, O.scaled_identity_guess(S_np), order=2, rule="monotone")
+    c1 = {"workload": WORKLOADS["gauss256"]["desc"] + ", FP64 path, 3rd-order series"}
+    for rule in ("monotone", "ratio"):
+        s, r = timed_solves(lambda: zf.refine(S, None, precision="fp64", stop=rule, out=Z), 100, 5)
+        Zn = Z.cpu().numpy()
+        c1[rule] = {"ms": round(s * 1e3, 4), "iters": r.iters, "evals": r.high_evals,
+                    "final_rms": r.final_rms, "oracle_rms": O.residual_rms(S_np, Zn)}
+        if rule == "monotone":
+            c1[rule]["oracle_iters"] = ref.iters
+            c1[rule]["rel_diff_vs_oracle"] = float(np.linalg.norm(Zn - ref.Z) / np.linalg.norm(ref.Z))
+            c1[rule]["lowdin_rel_err"] = lowdin_error(S_np, [Zn])[0]
+    out["gauss256_fp64"] = c1
+    print(f"[bench] gauss256 fp64: {c1['monotone']['ms']} ms", file=sys.stderr, flush=True)
+
+    # ill-conditioned cluster, N = 5049
+    S_np = inputs.workload("cluster5049", args.seed)
+    sub = argparse.Namespace(**vars(args))
+    sub.steps, sub.warmup, sub.fp64_steps = 5, 2, 2
+    r = run_single(sub, "cluster5049", S_np, with_profile=False, legs=("fp64",))
+    c3 = {"workload": WORKLOADS["cluster5049"]["desc"], "mixed": r["mixed"], "fp64": r.get("fp64"),
+          "checks": r["checks"]}
+    if r.get("fp64"):
+        c3["speedup_vs_fp64"] = round(r["fp64"]["ms"] / r["mixed"]["ms"], 3)
+    out["cluster5049"] = c3
+
+    # MD warm start (N = 3000) and the batch
+    sub = argparse.Namespace(**vars(args))
+    out["md3000"] = bench_md(sub)
+    sub = argparse.Namespace(**vars(args))
+    sub.steps, sub.warmup = 3, 1
+    out["batched512"] = bench_batched(sub)
+    torch.cuda.synchronize()
+    return out
 
 
 def bench_table1(args) -> int:
@@ -433,7 +595,7 @@ def bench_congruence(args) -> int:
     return 0
 
 
-def bench_md(args) -> int:
+def bench_md(args) -> dict:
     """MD-like warm start: frames of the N = 3000 Gaussian-kernel system with positions
     random-walking by N(0, 0.01 A) per coordinate; each frame refined from (a) the
     previous frame's Z, (b) the learned guess, (c) the scaled identity.  The network
@@ -492,11 +654,10 @@ def bench_md(args) -> int:
                               f"loss {losses[0]:.3g} -> {losses[-1]:.3g})"},
         "strategies": summary,
     }
-    print(json.dumps(line), flush=True)
-    return 0
+    return line
 
 
-def bench_batched(args) -> int:
+def bench_batched(args) -> dict:
     """512 Gaussian-kernel overlaps, N log-uniform in [64, 1024], condition number
     log-uniform in [10, 1e4], refined in one zf_refine_batched call per step.  Matrices
     start from the learned guess (per-matrix acceptance, scaled-identity fallback); the
@@ -521,6 +682,8 @@ def bench_batched(args) -> int:
     S = [torch.from_numpy(m).to("cuda:0") for m in mats]
     out = [torch.empty_like(s) for s in S]
     ns = [m.shape[0] for m in mats]
+    if getattr(args, "graph_sweeps", None) is not None:
+        zf.batched_set_graph_sweeps(args.graph_sweeps)
 
     def leg(kind):
         for _ in range(args.warmup):
@@ -532,15 +695,16 @@ def bench_batched(args) -> int:
             last = zf.refine_batched(S, out=out, guess=kind)
         torch.cuda.synchronize()
         step_s = (time.perf_counter() - t0) / args.steps
-        # the method's products per sweep, plus the S^2 product of each learned guess
+        # the method's irreducible flops, plus the symmetric S^2 of each learned guess
         flops = sum(alg_flops(n, 2, r.low_evals + r.high_evals,
                               (r.low_evals - 1) + max(r.high_evals - 1, 0))
-                    + (2.0 * n ** 3 if r.z0_used == zf.Z0_LEARNED else 0.0)
+                    + (float(n) ** 3 if r.z0_used == zf.Z0_LEARNED else 0.0)
                     for n, r in zip(ns, last.results))
         print(f"[bench] {kind}: {step_s * 1e3:.2f} ms per batch", file=sys.stderr, flush=True)
         return step_s, flops, last
 
     step_s, flops, last = leg("learned")
+    sweeps, launches = zf.batched_last_stats()
     worst = max(r.final_rms for r in last.results)
     from oracle import zf_oracle as O
     idx = sorted(set(np.linspace(0, count - 1, 8).astype(int).tolist()))
@@ -562,6 +726,8 @@ def bench_batched(args) -> int:
                               f"{args.seed + 1000}), 400 Adam steps, loss {losses[0]:.3g} -> "
                               f"{losses[-1]:.3g}"},
         "worst_final_rms": worst,
+        "graph": {"macro_sweeps": sweeps, "graph_launches": launches,
+                  "host_syncs": launches + 1},
         "mean_iters": float(np.mean([r.iters for r in last.results])),
         "mean_low_evals": float(np.mean([r.low_evals for r in last.results])),
         "learned_accepted": int(sum(r.z0_used == zf.Z0_LEARNED for r in last.results)),
@@ -572,8 +738,7 @@ def bench_batched(args) -> int:
                             "mean_low_evals": float(np.mean([r.low_evals for r in id_last.results])),
                             "worst_final_rms": max(r.final_rms for r in id_last.results)},
     }
-    print(json.dumps(line), flush=True)
-    return 0
+    return line
 
 
 if __name__ == "__main__":

@@ -161,10 +161,13 @@ int zf_refine_ex(const double* S, const double* Z0, int n, const zf_opts* opts, 
  *   hist        host[count * hist_cap]: matrix m's residual history at m * hist_cap.
  * Every matrix runs the recursion and stop test of zf_refine_ex; the matrices advance
  * in lockstep macro-sweeps of grouped matrix-core GEMMs (one persistent launch per
- * stage), replayed as a HIP graph, with the stop state kept on the device.  The
- * tile edge per matrix comes from the table of zf_batched_set_tiles /
- * zf_batched_autotune.  Returns the OR of the warnings, or the first failing
- * matrix's error (every result is still filled).  Synchronizes the stream.
+ * stage), with the stop state kept on the device.  Runs of macro-sweeps (8 by
+ * default, see zf_batched_set_graph_sweeps) are captured in one HIP graph; the host
+ * launches it and reads the live count once per launch, and kernels of macro-sweeps
+ * after every matrix has stopped return at once.  The tile edge per matrix comes from
+ * the table of
+ * zf_batched_set_tiles / zf_batched_autotune.  Returns the OR of the warnings, or the
+ * first failing matrix's error (every result is still filled).
  */
 int zf_refine_batched(int count, const double* const* S, const double* const* Z0, const int* n,
                       const zf_opts* opts, double* const* Z, zf_result* res, double* hist,
@@ -187,6 +190,18 @@ int zf_batched_autotune(const int* bucket_n, int nbuckets, int batch, int reps, 
 /* zf_batched_use_graph -- 1 (default): replay the captured macro-sweep graph; 0: launch
  * the same kernels eagerly (for checking the graph). */
 void zf_batched_use_graph(int on);
+
+/* zf_batched_set_graph_sweeps -- macro-sweeps per graph launch: k > 0 (default 8)
+ * launches graphs of k macro-sweeps until no matrix is live, reading the live count
+ * after each launch; 0 captures every macro-sweep the sweep caps allow (one launch and
+ * one synchronization per call, but each macro-sweep after the last stop still costs
+ * its launches).  Returns ZF_ERR_ARG for k < 0. */
+int zf_batched_set_graph_sweeps(int sweeps);
+
+/* zf_batched_last_stats -- of the last zf_refine_batched call: the macro-sweeps in which
+ * some matrix was still live, and the number of graph launches (either pointer may be
+ * NULL). */
+int zf_batched_last_stats(int* macro_sweeps, int* graph_launches);
 
 /* zf_batched_release -- free the batched path's cached arena, graph and stream. */
 void zf_batched_release(void);

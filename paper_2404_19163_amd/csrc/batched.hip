@@ -15,10 +15,17 @@
 //
 // Each grouped GEMM is one persistent launch over a static table of (matrix,
 // tile) tasks; a task whose matrix is not in that stage is skipped on the device,
-// so the macro-sweep is a fixed sequence of launches, captured once in a HIP graph
-// and replayed until every matrix is done.  The tile edge of each matrix (64 or
-// 128) comes from a table indexed by its order, filled by zf_batched_autotune or
-// left at its defaults.
+// so the macro-sweep is a fixed sequence of launches.  A run of macro-sweeps is
+// captured once in a HIP graph; every kernel of a macro-sweep first reads the
+// device-side count of live matrices and returns at once when it is zero, so
+// macro-sweeps past the last matrix's stop cost only their launches (about 50 us
+// each for the 512-matrix batch).  The graph holds 8 macro-sweeps by default and is
+// launched until the live count, read after each launch, is zero: one host
+// synchronization per 8 macro-sweeps and at most 7 idle ones.  (The 512-matrix batch
+// takes 13 macro-sweeps: 51.2-51.9 ms with 1, 2, 4 or 8 per graph, 56.5 ms with all
+// 113 that the caps allow in one graph.)  The tile edge of each
+// matrix (64 or 128) comes from a table indexed by its order, filled by
+// zf_batched_autotune or left at its defaults.
 //
 // Set-up (once, before the graph): split S; for matrices taking the learned guess
 // the grouped BF16x3 S^2 (stage S2), then per-matrix statistics and features, one
@@ -111,10 +118,11 @@ template <int T>
 __global__ void __launch_bounds__(X3G<T>::NT, 2)
     grouped_x3_kernel(const TileTask* __restrict__ tasks, const int* __restrict__ seg,
                       const BMat* __restrict__ mats, int op, double c1, double c2,
-                      double* partials) {
+                      double* partials, const int* __restrict__ live) {
   using CF = X3G<T>;
   __shared__ __attribute__((aligned(16))) u16 lds[2 * CF::STAGE_ELEMS];
   __shared__ double red[CF::NT / 64];
+  if (live && *live == 0) return;  // every matrix has stopped
   int t0, t1, step;
   xcd_run(seg, T == 128 ? 0 : 1, t0, t1, step);
   for (int t = t0; t < t1; t += step) {
@@ -198,9 +206,11 @@ __global__ void __launch_bounds__(X3G<T>::NT, 2)
 // 64-wide runs): four blocks per CU, the single path's choice.
 __global__ void __launch_bounds__(256, 4)
     grouped_f64_kernel(const TileTask* __restrict__ tasks, const int* __restrict__ seg,
-                       const BMat* __restrict__ mats, int op, double* partials) {
+                       const BMat* __restrict__ mats, int op, double* partials,
+                       const int* __restrict__ live) {
   __shared__ double lds[2 * F64_64::STAGE];
   __shared__ double red[4];
+  if (*live == 0) return;  // every matrix has stopped
   int t0, t1, step;
   xcd_run(seg, 1, t0, t1, step);
   for (int t = t0; t < t1; t += step) {
@@ -244,6 +254,8 @@ __global__ void __launch_bounds__(256, 4)
 __global__ void decide_kernel(BMat* mats, int count, const double* __restrict__ partials, int order,
                               int rule, int max_l, int max_h, int refine_on, int hist_cap,
                               int* remaining) {
+  // remaining[0]: matrices not yet done; remaining[1]: macro-sweeps that had any
+  if (remaining[0] == 0) return;
   __shared__ int live;
   if (threadIdx.x == 0) live = 0;
   __syncthreads();
@@ -308,7 +320,18 @@ __global__ void decide_kernel(BMat* mats, int count, const double* __restrict__ 
     if (M.action != ACT_DONE) atomicAdd(&live, 1);
   }
   __syncthreads();
-  if (threadIdx.x == 0) remaining[0] = live;
+  if (threadIdx.x == 0) {
+    remaining[0] = live;
+    remaining[1] += 1;
+  }
+}
+
+// remaining[0] = count (every matrix live), remaining[1] = 0 macro-sweeps
+__global__ void b_reset_kernel(int* remaining, int count) {
+  if (threadIdx.x == 0) {
+    remaining[0] = count;
+    remaining[1] = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -522,8 +545,10 @@ __global__ void __launch_bounds__(256) b_init_kernel(const BMat* __restrict__ ma
 }
 
 // FP32 master -> FP64 row-major and transposed for matrices entering the FP64 phase
-__global__ void __launch_bounds__(256) b_widen_kernel(const BMat* __restrict__ mats) {
+__global__ void __launch_bounds__(256) b_widen_kernel(const BMat* __restrict__ mats,
+                                                      const int* __restrict__ live) {
   __shared__ float tv[kET][kET + 1];
+  if (*live == 0) return;
   const BMat& M = mats[blockIdx.y];
   if (M.action != ACT_TRANSITION) return;
   int i0, j0;
@@ -566,6 +591,8 @@ static int g_tile_nb = 4;
 static int g_tile_max[16] = {128, 256, 512, 1 << 30};
 static int g_tile_edge[16] = {64, 64, 128, 128};
 static bool g_use_graph = true;
+static int g_graph_sweeps = 8;  // macro-sweeps per graph; 0 = every one the caps allow
+static int g_last_sweeps = 0, g_last_launches = 0;  // of the last call (zf_batched_last_stats)
 
 static int tile_for(int n) {
   for (int k = 0; k < g_tile_nb; ++k)
@@ -716,38 +743,43 @@ struct Launch {
   double* partials;
   int* remaining;
   int count, grid, order, rule, max_l, max_h, refine_on, hist_cap;
+  int graph_sweeps;  // macro-sweeps captured in one graph
   double c1, c2;
 };
 
 // Grouped BF16x3 stage: one launch per tile edge present (host copy hseg of the run
 // bounds decides which); grid is a multiple of 8.
+// live: the device-side count of live matrices (the kernels return at once when it
+// is zero), or nullptr outside the macro-sweep.
 static void x3_group(const TileTask* tasks, const int* seg, const int* hseg, const BMat* mats,
-                     int op, double c1, double c2, double* partials, int grid, hipStream_t st) {
+                     int op, double c1, double c2, double* partials, int grid, hipStream_t st,
+                     const int* live = nullptr) {
   if (hseg[8] > hseg[0])
     hipLaunchKernelGGL(grouped_x3_kernel<128>, dim3(grid), dim3(X3G<128>::NT), 0, st, tasks, seg,
-                       mats, op, c1, c2, partials);
+                       mats, op, c1, c2, partials, live);
   if (hseg[16] > hseg[8])
     hipLaunchKernelGGL(grouped_x3_kernel<64>, dim3(grid), dim3(X3G<64>::NT), 0, st, tasks, seg,
-                       mats, op, c1, c2, partials);
+                       mats, op, c1, c2, partials, live);
 }
 
 // one macro-sweep on stream st (captured into the graph, or run eagerly)
 static hipError_t macro_sweep(const Launch& L, hipStream_t st) {
-  x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_L1, 0.0, 0.0, L.partials, L.grid, st);
-  x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_L2, 0.0, 0.0, L.partials, L.grid, st);
+  const int* live = L.remaining;
+  x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_L1, 0.0, 0.0, L.partials, L.grid, st, live);
+  x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_L2, 0.0, 0.0, L.partials, L.grid, st, live);
   if (L.refine_on) {
     // 64-wide FP64 tiles fit four blocks per CU: twice the grid
     hipLaunchKernelGGL(grouped_f64_kernel, dim3(2 * L.grid), dim3(256), 0, st, L.ffull, L.ffseg,
-                       L.mats, (int)OP_H1, L.partials);
+                       L.mats, (int)OP_H1, L.partials, live);
     hipLaunchKernelGGL(grouped_f64_kernel, dim3(2 * L.grid), dim3(256), 0, st, L.fsym, L.fsseg,
-                       L.mats, (int)OP_H2, L.partials);
+                       L.mats, (int)OP_H2, L.partials, live);
   }
   hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, st, L.mats, L.count, L.partials, L.order,
                      L.rule, L.max_l, L.max_h, L.refine_on, L.hist_cap, L.remaining);
   if (L.refine_on)
-    hipLaunchKernelGGL(b_widen_kernel, dim3(L.etiles, L.count), dim3(256), 0, st, L.mats);
-  x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_U3, L.c1, L.c2, L.partials, L.grid, st);
-  x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_U4, 0.0, 0.0, L.partials, L.grid, st);
+    hipLaunchKernelGGL(b_widen_kernel, dim3(L.etiles, L.count), dim3(256), 0, st, L.mats, live);
+  x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_U3, L.c1, L.c2, L.partials, L.grid, st, live);
+  x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_U4, 0.0, 0.0, L.partials, L.grid, st, live);
   return hipGetLastError();
 }
 
@@ -897,6 +929,7 @@ static int batched_impl(int count, const double* const* S, const double* const* 
                        d_stats, d_coef);
   }
   hipLaunchKernelGGL(b_init_kernel, eg, dim3(256), 0, st, d_mats, d_Z0, d_S, d_g, d_coef);
+  hipLaunchKernelGGL(b_reset_kernel, dim3(1), dim3(64), 0, st, (int*)(mb + o_rem), count);
   BHIP_TRY(hipGetLastError());
 
   Launch L;
@@ -927,8 +960,12 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   L.hist_cap = hcap;
   L.c1 = 0.5;
   L.c2 = 0.375;
+  // every macro-sweep the caps allow: max_l low-phase evaluations after the first,
+  // the phase change, max_h FP64 evaluations after the first, and one to spare
+  const int max_macro = max_l + (with64 ? max_h + 1 : 0) + 2;
+  L.graph_sweeps = (g_graph_sweeps > 0 && g_graph_sweeps < max_macro) ? g_graph_sweeps : max_macro;
 
-  // graph of one macro-sweep, rebuilt when the layout changes
+  // graph of graph_sweeps macro-sweeps, rebuilt when the layout changes
   std::vector<char> key(sizeof(Launch));
   memcpy(key.data(), &L, sizeof(Launch));
   if (g_use_graph && (g_b.key != key || !g_b.exec)) {
@@ -938,7 +975,8 @@ static int batched_impl(int count, const double* const* S, const double* const* 
     }
     hipGraph_t graph = nullptr;
     BHIP_TRY(hipStreamBeginCapture(g_b.cap, hipStreamCaptureModeThreadLocal));
-    hipError_t ce = macro_sweep(L, g_b.cap);
+    hipError_t ce = hipSuccess;
+    for (int k = 0; k < L.graph_sweeps && ce == hipSuccess; ++k) ce = macro_sweep(L, g_b.cap);
     hipError_t ee = hipStreamEndCapture(g_b.cap, &graph);
     if (ce != hipSuccess || ee != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -954,17 +992,22 @@ static int batched_impl(int count, const double* const* S, const double* const* 
     g_b.key = key;
   }
 
-  const int max_macro = max_l + (with64 ? max_h + 1 : 0) + 2;
-  int sweeps = 0;
+  // Graph: launches of graph_sweeps macro-sweeps each until the live count is zero
+  // (graph_sweeps = every macro-sweep the caps allow: one launch, after which the
+  // output kernel and the copies of the results follow on the stream, so the call
+  // synchronizes once).  Eager: one macro-sweep at a time, the host reading the live
+  // count after each.
+  const int chunk = g_use_graph ? L.graph_sweeps : 1;
+  int launched = 0, launches = 0;
   for (;;) {
     if (g_use_graph) BHIP_TRY(hipGraphLaunch(g_b.exec, st));
     else BHIP_TRY(macro_sweep(L, st));
+    launched += chunk;
+    ++launches;
+    if (launched >= max_macro) break;
     BHIP_TRY(hipMemcpyAsync(g_b.pinned, L.remaining, sizeof(int), hipMemcpyDeviceToHost, st));
     BHIP_TRY(hipStreamSynchronize(st));
-    ++sweeps;
     if (g_b.pinned[0] == 0) break;
-    if (sweeps >= max_macro)
-      return set_error(ZF_ERR_HIP, "batched refinement did not finish in %d macro-sweeps", sweeps);
   }
   hipLaunchKernelGGL(b_output_kernel, eg, dim3(256), 0, st, d_mats, d_Z, with64 ? 1 : 0);
   BHIP_TRY(hipGetLastError());
@@ -972,7 +1015,13 @@ static int batched_impl(int count, const double* const* S, const double* const* 
   BHIP_TRY(hipMemcpyAsync(out.data(), d_mats, sizeof(BMat) * count, hipMemcpyDeviceToHost, st));
   std::vector<double> h((size_t)count * hcap);
   BHIP_TRY(hipMemcpyAsync(h.data(), mb + o_hist, 8 * h.size(), hipMemcpyDeviceToHost, st));
+  BHIP_TRY(hipMemcpyAsync(g_b.pinned, L.remaining, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   BHIP_TRY(hipStreamSynchronize(st));
+  g_last_sweeps = g_b.pinned[1];
+  g_last_launches = launches;
+  if (g_b.pinned[0] != 0)
+    return set_error(ZF_ERR_HIP, "batched refinement did not finish in %d macro-sweeps",
+                     launched);
 
   int ret = 0, first_err = 0, first_m = -1;
   for (int m = 0; m < count; ++m) {
@@ -1177,6 +1226,19 @@ int zf_batched_autotune(const int* bucket_n, int nbuckets, int batch, int reps, 
 }
 
 void zf_batched_use_graph(int on) { g_use_graph = on != 0; }
+
+int zf_batched_set_graph_sweeps(int sweeps) {
+  if (sweeps < 0) return set_error(ZF_ERR_ARG, "sweeps per graph must be >= 0 (got %d)", sweeps);
+  g_graph_sweeps = sweeps;
+  g_b.key.clear();
+  return 0;
+}
+
+int zf_batched_last_stats(int* macro_sweeps, int* graph_launches) {
+  if (macro_sweeps) *macro_sweeps = g_last_sweeps;
+  if (graph_launches) *graph_launches = g_last_launches;
+  return 0;
+}
 
 void zf_batched_release(void) { batch_release(); }
 

@@ -60,7 +60,8 @@ EXPORTS = ("zf_default_opts", "zf_refine", "zf_refine_ex", "zf_residual", "zf_re
            "zf_last_error", "zf_version", "zf_t_split", "zf_t_gemm", "zf_t_gershgorin",
            "zf_profile_enable", "zf_profile_reset", "zf_profile_read", "zf_refine_batched",
            "zf_batched_set_tiles", "zf_batched_get_tiles", "zf_batched_autotune",
-           "zf_batched_use_graph", "zf_batched_release", "zf_features", "zf_guess_label",
+           "zf_batched_use_graph", "zf_batched_set_graph_sweeps", "zf_batched_last_stats",
+           "zf_batched_release", "zf_features", "zf_guess_label",
            "zf_mlp_set_params", "zf_mlp_get_params", "zf_mlp_set_norm", "zf_mlp_train_step",
            "zf_mlp_grad", "zf_mlp_predict", "zf_mlp_save", "zf_mlp_load", "zf_congruence", "zf_t_ozaki")
 N_PARAMS = 4931
@@ -118,6 +119,10 @@ def lib() -> ctypes.CDLL:
     L.zf_batched_autotune.restype = i
     L.zf_batched_use_graph.argtypes = [i]
     L.zf_batched_use_graph.restype = None
+    L.zf_batched_set_graph_sweeps.argtypes = [i]
+    L.zf_batched_set_graph_sweeps.restype = i
+    L.zf_batched_last_stats.argtypes = [P(i), P(i)]
+    L.zf_batched_last_stats.restype = i
     L.zf_batched_release.argtypes = []
     L.zf_batched_release.restype = None
     F = P(ctypes.c_float)
@@ -277,6 +282,19 @@ def batched_autotune(bucket_n, batch: int = 32, reps: int = 5, stream=None):
 
 def batched_use_graph(on: bool = True) -> None:
     lib().zf_batched_use_graph(1 if on else 0)
+
+
+def batched_set_graph_sweeps(sweeps: int = 8) -> None:
+    """Macro-sweeps captured per graph launch (default 8; 0: every one the caps allow,
+    so one launch and one synchronization per call)."""
+    _check(lib().zf_batched_set_graph_sweeps(sweeps))
+
+
+def batched_last_stats():
+    """(macro-sweeps that had a live matrix, graph launches) of the last batched call."""
+    a, b = ctypes.c_int(0), ctypes.c_int(0)
+    lib().zf_batched_last_stats(ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def batched_release() -> None:

@@ -92,6 +92,37 @@ def test_graph_replay_equals_eager(zf, batch):
             assert a.hist == b.hist and a.iters == b.iters
 
 
+def test_graph_lengths_agree(zf, batch):
+    """One graph holding every macro-sweep the caps allow (one launch per call; the
+    macro-sweeps after every matrix stopped change nothing) and shorter graphs (the
+    live count read after each launch; the default holds 8) give bitwise the same
+    results and the same number of live macro-sweeps."""
+    mats, _ = batch
+    S = [_cuda(x) for x in mats]
+    zf.batched_set_graph_sweeps(0)
+    try:
+        one = zf.refine_batched(S)
+        sweeps, launches = zf.batched_last_stats()
+    finally:
+        zf.batched_set_graph_sweeps(8)
+    assert launches == 1
+    assert sweeps == max(r.low_evals + r.high_evals for r in one.results)
+    for k in (1, 3, 5, 8):
+        zf.batched_set_graph_sweeps(k)
+        try:
+            part = zf.refine_batched(S)
+            s_k, l_k = zf.batched_last_stats()
+        finally:
+            zf.batched_set_graph_sweeps(8)
+        assert s_k == sweeps
+        assert l_k == -(-sweeps // k)  # the launch holding the last live macro-sweep ends it
+        for a, b in zip(one.results, part.results):
+            assert torch.equal(a.Z, b.Z), k
+            assert a.hist == b.hist and a.iters == b.iters
+    with pytest.raises(zf.ZFError):
+        zf.batched_set_graph_sweeps(-1)
+
+
 def test_batched_given_guesses_and_refine_off(zf, batch):
     mats, refs = batch
     S = [_cuda(x) for x in mats[:4]]
