@@ -270,6 +270,19 @@ int zf_congruence(const double* H, const double* Z, int n, int precision, double
  * ZF_ERR_HIP. */
 int zf_residual(const double* S, const double* Z, int n, double* rms, void* stream);
 
+/* zf_residual_noalloc -- zf_residual for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * The same FP64 products and the same fixed-order norm, on a device array of the
+ * library (24 MiB per GPU, held until the process ends), for n <= 1024.
+ *   S, Z:    device n x n FP64 (S symmetric), read only.
+ *   rms_dev: device pointer to one double, receives ||Z^T S Z - I||_F / sqrt(n),
+ *            bitwise equal to zf_residual's value for the same inputs.
+ * Stream-ordered: enqueues its kernels on stream and returns without synchronizing.
+ * Allocates nothing.  Every call on one GPU uses that GPU's array: calls that overlap
+ * on one GPU (other streams or threads) race.  Errors: ZF_ERR_ARG (NULL pointer, n
+ * outside 1..1024), ZF_ERR_HIP. */
+int zf_residual_noalloc(const double* S, const double* Z, int n, double* rms_dev, void* stream);
+
 /* zf_release -- free every cached workspace of the current device. */
 void zf_release(void);
 

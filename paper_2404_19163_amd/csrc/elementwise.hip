@@ -284,7 +284,8 @@ hipError_t launch_unpad_f32(const float* src, int np, int n, double* dst, hipStr
 // ---------------------------------------------------------------------------
 // ||.||_F from per-tile partial sums: fixed summation order (bitwise repeatable).
 // ---------------------------------------------------------------------------
-__global__ void norm_finalize_kernel(const double* __restrict__ partials, int count, double* out) {
+__global__ void norm_finalize_kernel(const double* __restrict__ partials, int count, double* out,
+                                     double div) {
   __shared__ double red[256];
   double s = 0.0;
   for (int i = threadIdx.x; i < count; i += 256) s += partials[i];
@@ -294,11 +295,12 @@ __global__ void norm_finalize_kernel(const double* __restrict__ partials, int co
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sqrt(red[0]);
+  if (threadIdx.x == 0) out[0] = sqrt(red[0]) / div;
 }
 
-hipError_t launch_norm_finalize(const double* partials, int count, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(norm_finalize_kernel, dim3(1), dim3(256), 0, st, partials, count, out);
+hipError_t launch_norm_finalize(const double* partials, int count, double* out, hipStream_t st,
+                                double div) {
+  hipLaunchKernelGGL(norm_finalize_kernel, dim3(1), dim3(256), 0, st, partials, count, out, div);
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -989,6 +990,70 @@ int zf_residual(const double* S, const double* Z, int n, double* rms, void* stre
   ZF_TRY(delta_eval(c, AR_F64, AR_F64, 0, &e));
   if (g_prof.on) prof_harvest();
   *rms = e / sqrt((double)n);
+  g_err.clear();
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// zf_residual_noalloc: zf_residual's products on a fixed device array
+// ---------------------------------------------------------------------------
+// Layout (doubles): padded S | Z^T | A^T = Z^T S (each kNoAllocNp^2, row-major with
+// ld = np for the padded order np of the call) | norm partials.  Every call
+// overwrites what it reads before reading it, so nothing needs clearing; calls that
+// overlap on one GPU share the array and race.
+constexpr int kNoAllocMaxN = 1024;
+constexpr int kNoAllocNp = 1024;  // pad_order(kNoAllocMaxN)
+constexpr size_t kNoAllocMat = (size_t)kNoAllocNp * kNoAllocNp;
+constexpr int kNoAllocParts = (kNoAllocNp / 64) * (kNoAllocNp / 64);  // max_blocks(np, np)
+static __device__ __align__(256) double scratch[3 * kNoAllocMat + kNoAllocParts];
+
+// Device address of `scratch` on each device, looked up once per device with that
+// device current (host code uses these, never the array's own name).
+constexpr int kNoAllocMaxDevices = 64;
+static double* g_scratch_dev[kNoAllocMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+static int scratch_ptr(double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return fail(ZF_ERR_ARG, "device %d outside 0..%d", dev, kNoAllocMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(ZF_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    }
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return 0;
+}
+
+int zf_residual_noalloc(const double* S, const double* Z, int n, double* rms_dev, void* stream) {
+  if (!S || !Z || !rms_dev) return fail(ZF_ERR_ARG, "NULL argument");
+  if (n <= 0 || n > kNoAllocMaxN)
+    return fail(ZF_ERR_ARG, "n must be in 1..%d (got %d)", kNoAllocMaxN, n);
+  hipStream_t st = (hipStream_t)stream;
+  double* base = nullptr;
+  ZF_TRY(scratch_ptr(&base));
+  const int np = pad_order(n);
+  double* s64 = base;
+  double* zc = base + kNoAllocMat;
+  double* at = base + 2 * kNoAllocMat;
+  double* parts = base + 3 * kNoAllocMat;
+  HIP_TRY(launch_split_pad(S, n, n, np, nullptr, nullptr, s64, nullptr, false, 1, st));
+  HIP_TRY(launch_init_given(Z, n, np, nullptr, nullptr, zc, nullptr, nullptr, nullptr, nullptr, st));
+  EpiParams e1 = epi0(np, n), e2 = epi0(np, n);
+  e1.o64 = at;  // A^T = Z^T S
+  e2.beta = -1.0;  // delta = I - Z^T A, only its norm partials are kept
+  e2.gamma = 1.0;
+  e2.partials = parts;
+  HIP_TRY(launch_gemm_f64(zc, np, s64, np, np, np, np, false, e1, st));
+  HIP_TRY(launch_gemm_f64(zc, np, at, np, np, np, np, true, e2, st));
+  HIP_TRY(launch_norm_finalize(parts, f64_blocks(np, np, true), rms_dev, st, sqrt((double)n)));
   g_err.clear();
   return 0;
 }

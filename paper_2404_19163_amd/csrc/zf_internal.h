@@ -186,7 +186,9 @@ hipError_t launch_widen(const float* z32, int np, double* z64r, double* z64c, hi
                         int fmt = PAIR_BF16);
 hipError_t launch_unpad_f64(const double* src, int np, int n, double* dst, hipStream_t st);
 hipError_t launch_unpad_f32(const float* src, int np, int n, double* dst, hipStream_t st);
-hipError_t launch_norm_finalize(const double* partials, int count, double* out, hipStream_t st);
+// out[0] = sqrt(sum of the partials) / div (div = 1: the Frobenius norm itself)
+hipError_t launch_norm_finalize(const double* partials, int count, double* out, hipStream_t st,
+                                double div = 1.0);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
 // Tracing (zf_api.hip).

@@ -56,7 +56,7 @@ class Result(ctypes.Structure):
                 ("z0_used", ctypes.c_int)]
 
 
-EXPORTS = ("zf_default_opts", "zf_refine", "zf_refine_ex", "zf_residual", "zf_release",
+EXPORTS = ("zf_default_opts", "zf_refine", "zf_refine_ex", "zf_residual", "zf_release", "zf_residual_noalloc",
            "zf_last_error", "zf_version", "zf_t_split", "zf_t_gemm", "zf_t_gershgorin",
            "zf_profile_enable", "zf_profile_reset", "zf_profile_read", "zf_refine_batched",
            "zf_batched_set_tiles", "zf_batched_get_tiles", "zf_batched_autotune",
@@ -87,6 +87,8 @@ def lib() -> ctypes.CDLL:
     L.zf_refine_ex.restype = i
     L.zf_residual.argtypes = [vp, vp, i, P(d), vp]
     L.zf_residual.restype = i
+    L.zf_residual_noalloc.argtypes = [vp, vp, i, vp, vp]
+    L.zf_residual_noalloc.restype = i
     L.zf_congruence.argtypes = [vp, vp, i, i, vp, vp]
     L.zf_congruence.restype = i
     L.zf_release.argtypes = []
@@ -322,6 +324,16 @@ def residual(S: torch.Tensor, Z: torch.Tensor, stream=None) -> float:
     v = ctypes.c_double(0.0)
     _check(lib().zf_residual(_dev(S, "S", n), _dev(Z, "Z", n), n, ctypes.byref(v), _stream(stream)))
     return v.value
+
+
+def residual_noalloc(S: torch.Tensor, Z: torch.Tensor, out: torch.Tensor, stream=None) -> None:
+    """zf_residual_noalloc: the RMS residual into the device scalar `out` (float64, one
+    element), stream-ordered, without allocating device memory (n <= 1024)."""
+    n = S.shape[0]
+    if out.dtype != torch.float64 or out.numel() < 1 or not out.is_cuda:
+        raise ValueError("out must be a CUDA float64 tensor with at least one element")
+    _check(lib().zf_residual_noalloc(_dev(S, "S", n), _dev(Z, "Z", n), n, out.data_ptr(),
+                                     _stream(stream)))
 
 
 def congruence(H: torch.Tensor, Z: torch.Tensor, *, precision: str = "fp64",
