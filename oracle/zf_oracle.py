@@ -283,6 +283,98 @@ def emulated_residual(S: np.ndarray, Z: np.ndarray, s: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# FP64 products emulated through residues (Ozaki, Uchino & Imamura 2025, "Ozaki
+# scheme II"): each operand row is scaled by a power of two and truncated to an
+# integer of at most beta bits; the integer product is formed exactly (on the GPU
+# from its residues modulo L pairwise coprime moduli <= 256, one int8 product per
+# modulus, and the Chinese remainder theorem); the result is that exact product
+# scaled back and rounded to FP64.  Defined here by the exact product itself.
+# ---------------------------------------------------------------------------
+
+# pairwise coprime moduli, largest first; the first L are used
+CRT_MODULI = (256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199, 197, 193)
+CRT_MAX_BETA = 52
+
+
+def crt_beta(K: int, L: int) -> int:
+    """Largest beta with 2 K 2^(2 beta) <= M = product of the first L moduli (the exact
+    integer product of two K-term rows of beta-bit integers then lies strictly inside
+    (-M/2, M/2) and is fixed by its residues), capped at 52."""
+    M = 1
+    for m in CRT_MODULI[:L]:
+        M *= m
+    b = 0
+    while 2 * K * 4 ** (b + 1) <= M:
+        b += 1
+    return min(b, CRT_MAX_BETA)
+
+
+def crt_truncate(A: np.ndarray, beta: int) -> tuple[np.ndarray, np.ndarray]:
+    """Row i of A as integers trunc(A_ik 2^(beta - e_i)) (toward zero, |.| < 2^beta),
+    e_i the frexp exponent of max_k |A_ik| (0 for a zero row).  Exact in FP64 since
+    beta <= 52."""
+    A = np.asarray(A, dtype=np.float64)
+    m = np.max(np.abs(A), axis=1) if A.shape[1] else np.zeros(A.shape[0])
+    e = np.where(m > 0, np.frexp(m)[1], 0).astype(np.int64)
+    q = np.trunc(np.ldexp(A, (beta - e)[:, None]))
+    return q.astype(np.int64), e
+
+
+def _exact_int_product(P: np.ndarray, Q: np.ndarray) -> np.ndarray:
+    """P Q^T of int64 matrices with entries below 2^52 in magnitude, exactly, as an
+    object array of Python ints.  Each entry splits as x = x1 2^26 + x0 with
+    0 <= x0 < 2^26 and |x1| < 2^26, so each of the four partial products is below
+    2^52 in magnitude; summed over blocks of at most 1024 terms in int64 they stay
+    below 2^62, and the blocks and the parts are combined in Python integers."""
+    P = np.asarray(P, dtype=np.int64)
+    Q = np.asarray(Q, dtype=np.int64)
+    P0 = P & ((1 << 26) - 1)
+    P1 = (P - P0) >> 26
+    Q0 = Q & ((1 << 26) - 1)
+    Q1 = (Q - Q0) >> 26
+    out = np.zeros((P.shape[0], Q.shape[0]), dtype=object)
+    for k0 in range(0, P.shape[1], 1024):
+        k = slice(k0, k0 + 1024)
+        c11 = (P1[:, k] @ Q1[:, k].T).astype(object)
+        c10 = (P1[:, k] @ Q0[:, k].T).astype(object)
+        c01 = (P0[:, k] @ Q1[:, k].T).astype(object)
+        c00 = (P0[:, k] @ Q0[:, k].T).astype(object)
+        out = out + c11 * (1 << 52) + (c10 + c01) * (1 << 26) + c00
+    return out
+
+
+def crt_product(A: np.ndarray, B: np.ndarray, L: int) -> np.ndarray:
+    """C = A B^T (A: M x K, B: N x K) from beta-bit row truncations of both operands,
+    beta = crt_beta(K, L): C_ij = fl(C'_ij 2^(e_i + f_j - 2 beta)) with C' the exact
+    integer product of the truncated rows.  Error against A B^T:
+    |C - A B^T|_ij <= 2^(1 - beta) K 2^(e_i + f_j) (1 + 2^-beta) + one rounding."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    beta = crt_beta(A.shape[1], L)
+    Ai, ea = crt_truncate(A, beta)
+    Bi, eb = crt_truncate(B, beta)
+    C = _exact_int_product(Ai, Bi)
+    out = np.empty(C.shape)
+    for i in range(C.shape[0]):
+        for j in range(C.shape[1]):
+            # float() of a Python int rounds to nearest even; the power of two is exact
+            out[i, j] = math.ldexp(float(C[i, j]), int(ea[i] + eb[j]) - 2 * beta)
+    return out
+
+
+def crt_residual(S: np.ndarray, Z: np.ndarray, L: int) -> np.ndarray:
+    """delta = I - Z^T S Z with both products emulated through residues, in the order
+    of Sec. III.B (A^T = Z^T S, then Z^T A), the second taken from its upper triangle
+    and mirrored."""
+    S = np.asarray(S, dtype=np.float64)
+    Zt = np.ascontiguousarray(np.asarray(Z, dtype=np.float64).T)
+    At = crt_product(Zt, S, L)
+    X = crt_product(Zt, At, L)
+    X = np.triu(X) + np.triu(X, 1).T
+    return np.eye(S.shape[0]) - X
+
+
+# ---------------------------------------------------------------------------
 # closed forms
 # ---------------------------------------------------------------------------
 

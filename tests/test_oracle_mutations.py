@@ -1,5 +1,6 @@
 """The oracle's pins must catch plausible mistakes: each case plants one in the
 oracle (CPU only, via monkeypatch) and checks that a pin test then fails."""
+import math
 from fractions import Fraction
 
 import numpy as np
@@ -8,6 +9,7 @@ import pytest
 from oracle import zf_guess_oracle as G
 from oracle import zf_oracle as O
 from tests import test_oracle_coeffs as TC
+from tests import test_oracle_crt as TX
 from tests import test_oracle_pins as TP
 from tests import test_oracle_congruence as TH
 from tests import test_oracle_ozaki as TZ
@@ -53,6 +55,31 @@ def _ozaki_dropped_weight(A, B, s):
 
 def _ozaki_shifted(A, B, s):
     return 2.0 * _true_ozaki(A, B, s)
+
+
+_true_crt_truncate = O.crt_truncate
+
+
+def _crt_floor(A, beta):
+    """Rounds toward minus infinity instead of toward zero."""
+    A = np.asarray(A, dtype=np.float64)
+    m = np.max(np.abs(A), axis=1)
+    e = np.where(m > 0, np.frexp(m)[1], 0).astype(np.int64)
+    return np.floor(np.ldexp(A, (beta - e)[:, None])).astype(np.int64), e
+
+
+def _crt_global_exponent(A, beta):
+    """One exponent for the whole matrix instead of one per row."""
+    A = np.asarray(A, dtype=np.float64)
+    e = np.full(A.shape[0], np.frexp(np.max(np.abs(A)))[1], dtype=np.int64)
+    return np.trunc(np.ldexp(A, (beta - e)[:, None])).astype(np.int64), e
+
+
+def _crt_beta_one_more(K, L):
+    M = 1
+    for m in O.CRT_MODULI[:L]:
+        M *= m
+    return min(int(math.log2(M / (2 * K)) // 2) + 1, 52)
 
 
 def _truncating_split(a, fmt="bf16"):
@@ -109,6 +136,10 @@ MUTANTS = [
     ("congruence", _mirrored_congruence, lambda g: TH.test_exact_rational()),
     ("ozaki_product", _ozaki_dropped_weight, lambda g: TZ.test_product_within_bound_of_exact(3)),
     ("ozaki_product", _ozaki_shifted, lambda g: TZ.test_integer_matrices_are_exact()),
+    ("crt_truncate", _crt_floor, lambda g: TX.test_odd_symmetry_and_row_scaling()),
+    ("crt_truncate", _crt_global_exponent, lambda g: TX.test_odd_symmetry_and_row_scaling()),
+    ("crt_truncate", _crt_global_exponent, lambda g: TX.test_product_within_bound_of_exact(14)),
+    ("crt_beta", _crt_beta_one_more, lambda g: TX.test_beta_hand_values()),
     ("split", _truncating_split, lambda g: TS.test_bf16_rounding_edge_values()),
     ("stop_now", _nonstrict_stop, lambda g: TC.test_stop_rule_algorithm_2()),
     ("gershgorin_max_row_sum", _frobenius_bound, lambda g: TP.test_gershgorin_hand_matrix()),
