@@ -297,14 +297,16 @@ CRT_MAX_BETA = 52
 
 
 def crt_beta(K: int, L: int) -> int:
-    """Largest beta with 2 K 2^(2 beta) <= M = product of the first L moduli (the exact
-    integer product of two K-term rows of beta-bit integers then lies strictly inside
-    (-M/2, M/2) and is fixed by its residues), capped at 52."""
+    """Largest beta with 4 K 2^(2 beta) <= M = product of the first L moduli: the exact
+    integer product of two K-term rows of beta-bit integers then lies inside
+    (-M/4, M/4), so it is fixed by its residues and sits a quarter period away from
+    the ambiguous +-M/2 (the reconstruction rounds its quotient by M from a
+    floating-point estimate).  Capped at 52."""
     M = 1
     for m in CRT_MODULI[:L]:
         M *= m
     b = 0
-    while 2 * K * 4 ** (b + 1) <= M:
+    while 4 * K * 4 ** (b + 1) <= M:
         b += 1
     return min(b, CRT_MAX_BETA)
 

@@ -29,13 +29,14 @@ def test_moduli_pairwise_coprime_and_int8_residues():
 def test_beta_hand_values():
     """log2 of the product of the first 14 moduli is 110.16 (by hand: 8 + 7.994 +
     7.983 + 7.971 + 7.948 + 7.913 + 7.901 + 7.864 + 7.839 + 7.827 + 7.801 + 7.762 +
-    7.721 + 7.636), so 2 K 4^beta <= M gives beta = floor((110.16 - 1 - log2 K) / 2):
-    48 for K = 4096, 47 for K = 16384, 51 for K = 128; 15 moduli reach the cap 52 at
-    K = 4096; 13 moduli (log2 M = 102.52) give 44."""
+    7.721 + 7.636), so 4 K 4^beta <= M gives beta = floor((110.16 - 2 - log2 K) / 2):
+    48 for K = 4096, 47 for K = 16384, 50 for K = 128; 15 moduli (117.78) give 51 at
+    K = 4096, and 52 (the cap) at K = 128; 13 moduli (102.52) give 44."""
     assert O.crt_beta(4096, 14) == 48
     assert O.crt_beta(16384, 14) == 47
-    assert O.crt_beta(128, 14) == 51
-    assert O.crt_beta(4096, 15) == 52
+    assert O.crt_beta(128, 14) == 50
+    assert O.crt_beta(4096, 15) == 51
+    assert O.crt_beta(128, 15) == 52
     assert O.crt_beta(4096, 13) == 44
 
 

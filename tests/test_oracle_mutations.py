@@ -79,7 +79,7 @@ def _crt_beta_one_more(K, L):
     M = 1
     for m in O.CRT_MODULI[:L]:
         M *= m
-    return min(int(math.log2(M / (2 * K)) // 2) + 1, 52)
+    return min(int(math.log2(M / (4 * K)) // 2) + 1, 52)
 
 
 def _truncating_split(a, fmt="bf16"):
