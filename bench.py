@@ -67,7 +67,8 @@ def measured_traffic(kernel: str, n: int):
 KCLASS_DTYPE = {"gemm_x3": "bf16", "gemm_x3_sym": "bf16", "gemm_f64": "fp64", "gemm_f64_sym": "fp64",
                 "gemm_hh": "bf16", "gemm_hh_sym": "bf16", "gemm_f32": "fp32", "gemm_f32_sym": "fp32",
                 "gemm_x3f16": "bf16", "gemm_x3f16_sym": "bf16", "gemm_hhf16": "bf16",
-                "gemm_hhf16_sym": "bf16", "gemm_oz": "int8", "gemm_oz_sym": "int8"}
+                "gemm_hhf16_sym": "bf16", "gemm_oz": "int8", "gemm_oz_sym": "int8",
+                "gemm_crt": "int8", "gemm_crt_sym": "int8"}
 
 WORKLOADS = {
     "gauss4096": dict(n=4096, sigma=1.0,
@@ -181,7 +182,7 @@ def cpu_oracle_baseline(S_np, order: int, evals: int, updates: int, gpu_s: float
             "time_ratio_vs_gpu_1thread": round(est * t_eval1 / t_eval / gpu_s, 1)}
 
 
-def run_single(args, name: str, S_np, with_profile: bool, legs=("fp64", "emu")) -> dict:
+def run_single(args, name: str, S_np, with_profile: bool, legs=("fp64", "emu", "crt")) -> dict:
     """Mixed (headline) and FP64 legs of zf_refine on one matrix, with per-kernel
     times, roofline fractions and oracle checks."""
     import torch
@@ -194,7 +195,8 @@ def run_single(args, name: str, S_np, with_profile: bool, legs=("fp64", "emu")) 
     S = torch.from_numpy(S_np).to(dev)
     stream = torch.cuda.current_stream()
 
-    def run(precision, out, refine="f64_delta"):
+    def run(precision, out, refine=None):
+        refine = refine or getattr(args, "refine", "f64_delta")
         return zf.refine(S, None, order=args.order, precision=precision, out=out, stream=stream,
                          refine=refine)
 
@@ -244,6 +246,19 @@ def run_single(args, name: str, S_np, with_profile: bool, legs=("fp64", "emu")) 
                       "fp64_rms": zf.residual(S, Ze)}
         print(f"[bench] {name} mixed, emulated FP64 residual: {emu_s * 1e3:.3f} ms/step "
               f"rms={re_.final_rms:.3e}", file=sys.stderr, flush=True)
+
+    for mode in ("crt_first", "crt"):
+        if "crt" not in legs or args.fp64_steps <= 0 or n > 16384:
+            break
+        Zc = torch.empty_like(S)
+        crt_s, rc_ = timed_solves(lambda: run("bf16x3", Zc, mode), max(args.fp64_steps, 5), 1)
+        res[mode] = {"ms": round(crt_s * 1e3, 3), "evals": [rc_.low_evals, rc_.high_evals],
+                     "final_rms": rc_.final_rms,
+                     "moduli": int(os.environ.get("ZF_EMU_MODULI", "14")),
+                     "fp64_rms": zf.residual(S, Zc),
+                     "speedup_vs_fp64_residual": round(mixed_s / crt_s, 3)}
+        print(f"[bench] {name} mixed, residue-emulated residual ({mode}): {crt_s * 1e3:.3f} ms/step "
+              f"rms={rc_.final_rms:.3e}", file=sys.stderr, flush=True)
 
     # residuals and distances checked by the CPU oracle
     Zm_np = Zm.cpu().numpy()
@@ -320,6 +335,9 @@ def main() -> int:
     ap.add_argument("--headline-only", action="store_true",
                     help="only the N=4096 workload (skip the other configurations)")
     ap.add_argument("--mixed-only", action="store_true", help="skip the FP64 path (profiling runs)")
+    ap.add_argument("--refine", default="f64_delta",
+                    choices=["f64_delta", "crt_first", "crt", "emu", "f64_full"],
+                    help="refinement mode of the headline mixed path")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -410,6 +428,8 @@ def main() -> int:
         # both legs timed without per-GEMM events
         "speedup_vs_fp64": round(fp64["ms"] / mixed["ms_without_events"], 3) if fp64 else None,
         "mixed_emulated_residual": r.get("emu"),
+        "mixed_crt_first_residual": r.get("crt_first"),
+        "mixed_crt_residual": r.get("crt"),
         "checks": r["checks"],
         "kernels": kernel_table(prof, n, total_s),
         "roofline": roofline(prof, n, total_s),
@@ -452,9 +472,9 @@ def other_configs(args) -> dict:
     S_np = inputs.workload("cluster5049", args.seed)
     sub = argparse.Namespace(**vars(args))
     sub.steps, sub.warmup, sub.fp64_steps = 5, 2, 2
-    r = run_single(sub, "cluster5049", S_np, with_profile=False, legs=("fp64",))
+    r = run_single(sub, "cluster5049", S_np, with_profile=False, legs=("fp64", "crt"))
     c3 = {"workload": WORKLOADS["cluster5049"]["desc"], "mixed": r["mixed"], "fp64": r.get("fp64"),
-          "checks": r["checks"]}
+          "crt_first": r.get("crt_first"), "crt": r.get("crt"), "checks": r["checks"]}
     if r.get("fp64"):
         c3["speedup_vs_fp64"] = round(r["fp64"]["ms"] / r["mixed"]["ms"], 3)
     out["cluster5049"] = c3

@@ -85,12 +85,24 @@ enum zf_refine_mode {
   ZF_REFINE_F64_FULL = 2,  /* FP64 delta and FP64 correction                          */
   ZF_REFINE_F32 = 3,       /* FP32 delta, stop norm and correction (Algorithm 3 with
                               FP32[Z], the "+refi" of Table I in single precision)    */
-  ZF_REFINE_EMU = 4        /* delta and stop norm from FP64 products emulated on the
+  ZF_REFINE_EMU = 4,       /* delta and stop norm from FP64 products emulated on the
                               int8 matrix cores (7-bit integer slices, Ozaki scheme;
                               ZF_EMU_SLICES = 3..8 slices, default 7), BF16x3
                               correction.  Each product's error is below
                               (s+1) 2^-7s n 2^(e_i+f_j), e_i, f_j the exponents of the
                               largest entries of the operand rows; n <= 16384.       */
+  ZF_REFINE_CRT = 5,       /* delta and stop norm from FP64 products emulated through
+                              residues on the int8 matrix cores (rows truncated to
+                              beta-bit integers, one int8 product per modulus, Chinese
+                              remainder theorem; Ozaki, Uchino & Imamura's scheme II;
+                              ZF_EMU_MODULI = 8..15 moduli, default 14, beta = 48 at
+                              n = 4096), BF16x3 correction.  Each product's error is
+                              below 2^(1-beta) n 2^(e_i+f_j) plus a rounding;
+                              n <= 16384.                                             */
+  ZF_REFINE_CRT_FIRST = 6  /* as ZF_REFINE_F64_DELTA, but the refinement phase's first
+                              delta comes from the residue-emulated products of
+                              ZF_REFINE_CRT; every later evaluation, so the stopping
+                              norm and the final residual, is FP64.  n <= 16384.      */
 };
 
 typedef struct {
@@ -348,6 +360,22 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
 int zf_t_ozaki(int slices, int sym, int m, int nn, int k, const double* A, const double* B,
                double alpha, const double* D, double beta, double gamma, double* C,
                double* norm_sq, void* stream);
+
+/*
+ * zf_t_crt -- zf_t_gemm's product and epilogue with A B^T emulated through residues
+ * (the refinement residual's arithmetic under ZF_REFINE_CRT): row i of A is scaled
+ * by 2^(beta - e_i) (e_i the frexp exponent of its largest magnitude) and truncated
+ * toward zero to an integer; with M the product of the first `moduli` (2..15) of the
+ * pairwise coprime moduli 256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223,
+ * 217, 211, 199, 197, beta is the largest value with 4 k 4^beta <= M (at most 52).
+ * The exact integer product of the truncated rows is formed from one int8 product
+ * per modulus and the Chinese remainder theorem, then scaled by 2^(e_i + f_j -
+ * 2 beta).  max(m, nn, k) <= 16384.  A row holding a non-finite entry gives NaN
+ * products.
+ */
+int zf_t_crt(int moduli, int sym, int m, int nn, int k, const double* A, const double* B,
+             double alpha, const double* D, double beta, double gamma, double* C,
+             double* norm_sq, void* stream);
 
 /* zf_t_gershgorin -- g = max_i sum_j |S_ij| (host double) for device S (n x n). */
 int zf_t_gershgorin(const double* S, int n, double* g, void* stream);

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["gemm.hip", "elementwise.hip", "zf_api.hip", "batched.hip", "guess.hip", "ozaki.hip"]
+SOURCES = ["gemm.hip", "elementwise.hip", "zf_api.hip", "batched.hip", "guess.hip", "ozaki.hip",
+           "crt.hip"]
 OUT = os.path.join(PKG, "libzf.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

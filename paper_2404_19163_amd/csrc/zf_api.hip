@@ -114,12 +114,12 @@ static int pad_order(int n) { return n >= 1024 ? round_up(n, 256) : round_up(n, 
 // ---------------------------------------------------------------------------
 enum KClass {
   K_X3 = 0, K_X3_SYM, K_F64, K_F64_SYM, K_HH, K_HH_SYM, K_F32, K_F32_SYM, K_X3F16, K_X3F16_SYM,
-  K_HHF16, K_HHF16_SYM, K_OZ, K_OZ_SYM, K_COUNT
+  K_HHF16, K_HHF16_SYM, K_OZ, K_OZ_SYM, K_CRT, K_CRT_SYM, K_COUNT
 };
 static const char* kClassName[K_COUNT] = {
     "gemm_x3", "gemm_x3_sym", "gemm_f64", "gemm_f64_sym", "gemm_hh", "gemm_hh_sym",
     "gemm_f32", "gemm_f32_sym", "gemm_x3f16", "gemm_x3f16_sym", "gemm_hhf16", "gemm_hhf16_sym",
-    "gemm_oz", "gemm_oz_sym"};
+    "gemm_oz", "gemm_oz_sym", "gemm_crt", "gemm_crt_sym"};
 
 struct PendingEvent {
   hipEvent_t a, b;
@@ -188,6 +188,11 @@ struct Workspace {
   bool has_oz = false;
   signed char *oz_s = nullptr, *oz_z = nullptr, *oz_a = nullptr;
   int *oz_es = nullptr, *oz_ez = nullptr, *oz_ea = nullptr;
+  // emulated FP64 (residues): planes of S, Z^T and A^T, row exponents, product residues
+  bool has_crt = false;
+  signed char *cr_s = nullptr, *cr_z = nullptr, *cr_a = nullptr;
+  int *cr_es = nullptr, *cr_ez = nullptr, *cr_ea = nullptr;
+  unsigned char* cr_rho = nullptr;
   // scalars
   double *partials = nullptr, *err_dev = nullptr, *rowsum = nullptr, *g_dev = nullptr;
   double *gscr = nullptr, *cg = nullptr;  // learned-guess scratch (8192) and coefficients (8)
@@ -225,13 +230,15 @@ static int ws_alloc(Workspace& w, T** out, size_t elems) {
 
 // Allocate every buffer of a workspace for order np with the given parts.  On any
 // failure the partly built workspace is freed again and the error returned.
-static int ws_build(Workspace& w, int dev, int np, bool x3, bool f64, bool f32, bool oz) {
+static int ws_build(Workspace& w, int dev, int np, bool x3, bool f64, bool f32, bool oz,
+                    bool crt) {
   w.device = dev;
   w.np = np;
   w.has_x3 = x3;
   w.has_f64 = f64;
   w.has_f32 = f32;
   w.has_oz = oz;
+  w.has_crt = crt;
   const size_t m = (size_t)np * np;
   const int tiles = max_blocks(np, np);
   ZF_TRY(ws_alloc(w, &w.partials, tiles));
@@ -296,6 +303,15 @@ static int ws_build(Workspace& w, int dev, int np, bool x3, bool f64, bool f32, 
     ZF_TRY(ws_alloc(w, &w.oz_ez, np));
     ZF_TRY(ws_alloc(w, &w.oz_ea, np));
   }
+  if (crt) {
+    ZF_TRY(ws_alloc(w, &w.cr_s, m * kCrtMaxModuli));
+    ZF_TRY(ws_alloc(w, &w.cr_z, m * kCrtMaxModuli));
+    ZF_TRY(ws_alloc(w, &w.cr_a, m * kCrtMaxModuli));
+    ZF_TRY(ws_alloc(w, &w.cr_rho, m * kCrtMaxModuli));
+    ZF_TRY(ws_alloc(w, &w.cr_es, np));
+    ZF_TRY(ws_alloc(w, &w.cr_ez, np));
+    ZF_TRY(ws_alloc(w, &w.cr_ea, np));
+  }
   return 0;
 }
 
@@ -305,22 +321,23 @@ static int ws_build(Workspace& w, int dev, int np, bool x3, bool f64, bool f32, 
 // of the new workspace is released and the cache is left empty (np = 0, no parts),
 // so the next call allocates afresh instead of reusing null pointers.
 static int ws_get(int np, bool need_x3, bool need_f64, Workspace** out, bool need_f32 = false,
-                  bool need_oz = false) {
+                  bool need_oz = false, bool need_crt = false) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   Workspace& w = g_ws;
   if (w.device != dev || w.np < np || (need_x3 && !w.has_x3) || (need_f64 && !w.has_f64) ||
-      (need_f32 && !w.has_f32) || (need_oz && !w.has_oz)) {
+      (need_f32 && !w.has_f32) || (need_oz && !w.has_oz) || (need_crt && !w.has_crt)) {
     const bool same = w.device == dev;
     const bool x3 = need_x3 || (same && w.has_x3);
     const bool f64 = need_f64 || (same && w.has_f64);
     const bool f32 = need_f32 || (same && w.has_f32);
     const bool oz = need_oz || (same && w.has_oz);
+    const bool crt = need_crt || (same && w.has_crt);
     const int np_new = (same && w.np > np) ? w.np : np;
     ws_free(w);
     w.device = -1;
     Workspace nw;
-    const int rc = ws_build(nw, dev, np_new, x3, f64, f32, oz);
+    const int rc = ws_build(nw, dev, np_new, x3, f64, f32, oz, crt);
     if (rc < 0) {
       ws_free(nw);
       return rc;
@@ -430,6 +447,29 @@ static int gemm_oz(const signed char* A, const int* ea, const signed char* B, co
   return 0;
 }
 
+// Emulated FP64 product through residues (L moduli, K valid terms).
+static int gemm_crt(const signed char* A, const int* ea, const signed char* B, const int* eb,
+                    int np, int L, int K, bool sym, unsigned char* rho, const EpiParams& ep,
+                    hipStream_t st) {
+  PendingEvent pe{};
+  const bool prof = g_prof.on;
+  if (prof) {
+    pe.a = take_event();
+    pe.b = take_event();
+    pe.cls = sym ? K_CRT_SYM : K_CRT;
+    // executed int8 matrix-core operations: L products of 2 * 256^2 * np per launched tile
+    const double t = np / 256;
+    pe.flops = (double)L * 2.0 * (sym ? t * (t + 1) / 2 : t * t) * 65536.0 * (double)np;
+    HIP_TRY(hipEventRecord(pe.a, st));
+  }
+  HIP_TRY(launch_crt_product(A, ea, B, eb, np, L, K, sym, rho, ep, st));
+  if (prof) {
+    HIP_TRY(hipEventRecord(pe.b, st));
+    g_prof.pending.push_back(pe);
+  }
+  return 0;
+}
+
 // ---------------------------------------------------------------------------
 // the sweep
 // ---------------------------------------------------------------------------
@@ -437,7 +477,8 @@ static int gemm_oz(const signed char* A, const int* ea, const signed char* B, co
 // (h)(h)+(h)(l)+(l)(h) scheme (X3) or the (h)(h) scheme (HH), FP32 ("single") or
 // FP64 matrix-core GEMMs (Table I).
 // AR_EMU: FP64 residual emulated with integer slices on the int8 matrix cores.
-enum Arith { AR_X3 = 0, AR_HH, AR_F32, AR_F64, AR_X3F16, AR_HHF16, AR_EMU };
+// AR_CRT: FP64 residual emulated through residues on the int8 matrix cores.
+enum Arith { AR_X3 = 0, AR_HH, AR_F32, AR_F64, AR_X3F16, AR_HHF16, AR_EMU, AR_CRT };
 
 static bool ar_pairs(Arith a) {
   return a == AR_X3 || a == AR_HH || a == AR_X3F16 || a == AR_HHF16;
@@ -456,6 +497,9 @@ struct Ctx {
   double sigma;     // power-of-two scale of the FP16 delta pairs (FP16 halves only)
   int oz_slices = 7;     // slices per operand of the emulated residual
   bool oz_s_ready = false;  // S's slices are in the workspace (once per call)
+  int crt_moduli = 14;       // moduli of the residue-emulated residual
+  bool crt_s_ready = false;  // S's residues are in the workspace (once per call)
+  bool crt_first = false;    // only the refinement phase's first evaluation uses AR_CRT
   bool log = false;         // ZF_LOG: one JSON line per residual evaluation
 };
 
@@ -519,6 +563,19 @@ static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
     e2.o64 = e2.ot64 = w.d64;
     ZF_TRY(gemm_oz(w.oz_z, w.oz_ez, w.oz_a, w.oz_ea, np, s, true, e2, c.st));
     blocks = oz_blocks(np, true);
+  } else if (da == AR_CRT) {  // the same two products through residues, A^T kept in FP64
+    const int L = c.crt_moduli;
+    if (!c.crt_s_ready) {
+      HIP_TRY(launch_crt_residues(w.s64, np, L, c.n, w.cr_s, w.cr_es, c.st));
+      c.crt_s_ready = true;
+    }
+    HIP_TRY(launch_crt_residues(w.z64c[cur], np, L, c.n, w.cr_z, w.cr_ez, c.st));
+    e1.o64 = w.a64t;
+    ZF_TRY(gemm_crt(w.cr_z, w.cr_ez, w.cr_s, w.cr_es, np, L, c.n, false, w.cr_rho, e1, c.st));
+    HIP_TRY(launch_crt_residues(w.a64t, np, L, c.n, w.cr_a, w.cr_ea, c.st));
+    e2.o64 = e2.ot64 = w.d64;
+    ZF_TRY(gemm_crt(w.cr_z, w.cr_ez, w.cr_a, w.cr_ea, np, L, c.n, true, w.cr_rho, e2, c.st));
+    blocks = crt_blocks(np, true);
   } else if (da == AR_F32) {
     e1.o32 = w.a32t;
     ZF_TRY(gemm_f32(w.zc32[cur], w.s32, np, false, e1, c.st));
@@ -563,7 +620,7 @@ static int build_q(Ctx& c, Arith da, Arith ca, QRef* q) {
     EpiParams e = epi0(np, c.n);
     e.alpha = c.c[k] * sg;
     e.beta = ((k == m - 1) ? c.c[m] : 1.0) / sg;
-    if (da == AR_F64 || da == AR_EMU) e.d64 = w.d64;
+    if (da == AR_F64 || da == AR_EMU || da == AR_CRT) e.d64 = w.d64;
     else if (da == AR_F32 || f16) e.d32 = w.dl32;
     else {
       e.dhi = w.d_hi;
@@ -650,15 +707,15 @@ struct PhaseOut {
 // One phase of Algorithm 2: evaluate, stop test, update, ping-pong.
 static int run_phase(Ctx& c, Arith da, Arith ca, bool high, int stop_rule, int max_updates,
                      int& cur, std::vector<double>& hist, PhaseOut& out) {
-  static const char* kName[7] = {"BF16x3", "BF16",   "FP32",         "FP64",
-                                 "FP16x3", "FP16", "emulated FP64"};
+  static const char* kName[8] = {"BF16x3", "BF16", "FP32",          "FP64",
+                                 "FP16x3", "FP16", "emulated FP64", "residue-emulated FP64"};
   TraceRange phase_range(high ? "zf.phase_high" : "zf.phase_low");
   double prev = 0.0;
   for (int it = 0;; ++it) {
     double err = 0.0;
     {
       TraceRange r("zf.residual_eval");
-      ZF_TRY(delta_eval(c, da, ca, cur, &err));
+      ZF_TRY(delta_eval(c, (high && it == 0 && c.crt_first) ? AR_CRT : da, ca, cur, &err));
     }
     out.evals++;
     hist.push_back(err);
@@ -670,7 +727,8 @@ static int run_phase(Ctx& c, Arith da, Arith ca, bool high, int stop_rule, int m
     if (c.log)
       log_line("\"event\": \"eval\", \"n\": %d, \"arith\": \"%s\", \"phase\": \"%s\", \"it\": %d, "
                "\"err_f\": %.17g, \"rms\": %.6e, \"stop\": %s",
-               c.n, kName[da], high ? "high" : "low", it, err, err / sqrt((double)c.n),
+               c.n, kName[(high && it == 0 && c.crt_first) ? AR_CRT : da], high ? "high" : "low",
+               it, err, err / sqrt((double)c.n),
                stop ? "true" : "false");
     if (!isfinite(err))
       return fail(ZF_ERR_NONFINITE, "residual norm is not finite at %s sweep %d", kName[da], it);
@@ -752,6 +810,14 @@ static int oz_slices_env() {
   return (v >= 3 && v <= kOzMaxSlices) ? v : 7;
 }
 
+// Moduli of the residue-emulated residual: 14 (beta = 48 at K = 4096, 47 at 16384);
+// ZF_EMU_MODULI (8..15) overrides (tuning).
+static int crt_moduli_env() {
+  const char* env = getenv("ZF_EMU_MODULI");
+  const int v = env ? atoi(env) : 14;
+  return (v >= 8 && v <= kCrtMaxModuli) ? v : 14;
+}
+
 static int refine_core(const double* S, const double* Z0, int n, const zf_opts& o, double* Z,
                        zf_result* res, double* hist, int hist_cap, hipStream_t st, bool log) {
   if (!S || !Z) return fail(ZF_ERR_ARG, "S and Z must be non-NULL device pointers");
@@ -761,10 +827,15 @@ static int refine_core(const double* S, const double* Z0, int n, const zf_opts& 
     return fail(ZF_ERR_ARG, "precision %d is not supported", o.precision);
   if (o.stop != ZF_STOP_RATIO && o.stop != ZF_STOP_MONOTONE)
     return fail(ZF_ERR_ARG, "unknown stop rule %d", o.stop);
-  if (o.refine < ZF_REFINE_OFF || o.refine > ZF_REFINE_EMU)
+  if (o.refine < ZF_REFINE_OFF || o.refine > ZF_REFINE_CRT_FIRST)
     return fail(ZF_ERR_ARG, "unknown refine mode %d", o.refine);
   if (o.refine == ZF_REFINE_EMU && o.precision != ZF_FP64 && pad_order(n) > kOzMaxOrder)
     return fail(ZF_ERR_ARG, "the emulated FP64 residual supports n <= %d (got %d)", kOzMaxOrder, n);
+  const bool crt_mode = o.precision != ZF_FP64 &&
+                        (o.refine == ZF_REFINE_CRT || o.refine == ZF_REFINE_CRT_FIRST);
+  if (crt_mode && round_up(n, 256) > kCrtMaxOrder)
+    return fail(ZF_ERR_ARG, "the residue-emulated residual supports n <= %d (got %d)",
+                kCrtMaxOrder, n);
   if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(ZF_ERR_ARG, "bad hist buffer");
   if (n > 46000) return fail(ZF_ERR_ARG, "n = %d exceeds the supported maximum 46000", n);
   if (o.z0 != ZF_Z0_GIVEN && o.z0 != ZF_Z0_SCALED_IDENTITY && o.z0 != ZF_Z0_LEARNED)
@@ -782,18 +853,25 @@ static int refine_core(const double* S, const double* Z0, int n, const zf_opts& 
                    : o.precision == ZF_FP16   ? AR_HHF16
                                               : AR_F32;
   const bool refine = !fp64_only && o.refine != ZF_REFINE_OFF;
-  const Arith hd = o.refine == ZF_REFINE_F32 ? AR_F32 : o.refine == ZF_REFINE_EMU ? AR_EMU : AR_F64;
-  const Arith hc = (o.refine == ZF_REFINE_F64_DELTA || o.refine == ZF_REFINE_EMU) ? AR_X3 : hd;
-  const bool high = refine && (hd == AR_F64 || hd == AR_EMU);  // FP64 master
+  const Arith hd = o.refine == ZF_REFINE_F32   ? AR_F32
+                   : o.refine == ZF_REFINE_EMU ? AR_EMU
+                   : o.refine == ZF_REFINE_CRT ? AR_CRT
+                                               : AR_F64;  // CRT_FIRST: AR_CRT on the first only
+  const Arith hc = (o.refine == ZF_REFINE_F64_DELTA || o.refine == ZF_REFINE_EMU || crt_mode)
+                       ? AR_X3
+                       : hd;
+  const bool high = refine && (hd == AR_F64 || hd == AR_EMU || hd == AR_CRT);  // FP64 master
   const bool learned = !Z0 && o.z0 == ZF_Z0_LEARNED;
   const bool need_pairs = ar_pairs(la) || (refine && ar_pairs(hc));
   const bool need_f32 = la == AR_F32 || ar_f16(la) || (refine && hd == AR_F32);
   const bool use_h = fp64_only || high;
   const bool mixed = !fp64_only;  // FP32 master Z in the first phase
   const bool s_pairs = ar_pairs(la);
-  const int np = pad_order(n);
+  // the residue products run 256-wide tiles only
+  const int np = crt_mode ? round_up(n, 256) : pad_order(n);
   Workspace* w = nullptr;
-  ZF_TRY(ws_get(np, need_pairs, use_h || learned, &w, need_f32, refine && hd == AR_EMU));
+  ZF_TRY(ws_get(np, need_pairs, use_h || learned, &w, need_f32, refine && hd == AR_EMU,
+                crt_mode));
 
   Ctx c;
   c.w = w;
@@ -805,6 +883,9 @@ static int refine_core(const double* S, const double* Z0, int n, const zf_opts& 
   c.sigma = 1.0;
   c.oz_slices = oz_slices_env();
   c.oz_s_ready = false;
+  c.crt_moduli = crt_moduli_env();
+  c.crt_s_ready = false;
+  c.crt_first = o.refine == ZF_REFINE_CRT_FIRST;
   c.log = log;
   const int s_fmt = ar_f16(la) ? 2 : 1;  // split format of S: FP16 or BF16 halves
   series(o.order, c.c);
@@ -1229,22 +1310,27 @@ int zf_t_split(const double* a, int64_t count, uint16_t* hi, uint16_t* lo, int f
   return 0;
 }
 
-// precision < 0: the emulated product with oz_slices slices (zf_t_ozaki)
+// precision -1: the emulated product with oz_slices slices (zf_t_ozaki); precision -2:
+// the residue-emulated product with oz_slices moduli (zf_t_crt)
 static int t_gemm_impl(int precision, int oz_slices, int sym, int m, int nn, int k,
                        const double* A, const double* B, double alpha, const double* D,
                        double beta, double gamma, double* C, double* norm_sq, void* stream) {
   if (!A || !B || !C || m <= 0 || nn <= 0 || k <= 0) return fail(ZF_ERR_ARG, "bad gemm arguments");
   if (sym && m != nn) return fail(ZF_ERR_ARG, "symmetric mode needs m == nn");
-  const bool oz = precision < 0;
-  if (!oz && precision > ZF_FP16) return fail(ZF_ERR_ARG, "precision %d not supported", precision);
+  const bool crt = precision == -2;
+  const bool oz = precision == -1;
+  if (!oz && !crt && (precision < 0 || precision > ZF_FP16))
+    return fail(ZF_ERR_ARG, "precision %d not supported", precision);
   if (oz && (oz_slices < 1 || oz_slices > kOzMaxSlices))
     return fail(ZF_ERR_ARG, "slices must be in 1..%d (got %d)", kOzMaxSlices, oz_slices);
+  if (crt && (oz_slices < 2 || oz_slices > kCrtMaxModuli))
+    return fail(ZF_ERR_ARG, "moduli must be in 2..%d (got %d)", kCrtMaxModuli, oz_slices);
   hipStream_t st = (hipStream_t)stream;
   // pad every operand to a common square tile multiple
   int np = m > nn ? m : nn;
   if (k > np) np = k;
   np = round_up(np, 256);
-  if (oz && np > kOzMaxOrder)
+  if ((oz && np > kOzMaxOrder) || (crt && np > kCrtMaxOrder))
     return fail(ZF_ERR_ARG, "emulated products support dimensions up to %d", kOzMaxOrder);
   const size_t e = (size_t)np * np;
   std::vector<void*> tmp;
@@ -1295,7 +1381,21 @@ static int t_gemm_impl(int precision, int oz_slices, int sym, int m, int nn, int
                  : precision == ZF_FP16X3 ? PM_X3F16
                  : precision == ZF_FP16   ? PM_HHF16
                                           : PM_X3;
-  if (he == hipSuccess && oz) {
+  if (he == hipSuccess && crt) {
+    signed char *as, *bs;
+    unsigned char* rho;
+    int *ea, *eb;
+    if ((rc = alloc(e * oz_slices, (void**)&as)) || (rc = alloc(e * oz_slices, (void**)&bs)) ||
+        (rc = alloc(e * oz_slices, (void**)&rho)) || (rc = alloc((size_t)np * 4, (void**)&ea)) ||
+        (rc = alloc((size_t)np * 4, (void**)&eb))) {
+      cleanup();
+      return rc;
+    }
+    he = launch_crt_residues(a64, np, oz_slices, k, as, ea, st);
+    if (he == hipSuccess) he = launch_crt_residues(b64, np, oz_slices, k, bs, eb, st);
+    if (he == hipSuccess)
+      he = launch_crt_product(as, ea, bs, eb, np, oz_slices, k, sym != 0, rho, ep, st);
+  } else if (he == hipSuccess && oz) {
     signed char *as, *bs;
     int *ea, *eb;
     if ((rc = alloc(e * oz_slices, (void**)&as)) || (rc = alloc(e * oz_slices, (void**)&bs)) ||
@@ -1335,7 +1435,8 @@ static int t_gemm_impl(int precision, int oz_slices, int sym, int m, int nn, int
       cleanup();
       return rc;
     }
-    const int nb = oz      ? oz_blocks(np, sym != 0)
+    const int nb = crt     ? crt_blocks(np, sym != 0)
+                   : oz    ? oz_blocks(np, sym != 0)
                    : pairs ? x3_blocks(np, np, sym != 0)
                    : precision == ZF_FP32 ? f32_blocks(np, np, sym != 0)
                                           : f64_blocks(np, np, sym != 0);
@@ -1358,6 +1459,12 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
               void* stream) {
   if (precision < ZF_FP64) return fail(ZF_ERR_ARG, "precision %d not supported", precision);
   return t_gemm_impl(precision, 0, sym, m, nn, k, A, B, alpha, D, beta, gamma, C, norm_sq, stream);
+}
+
+int zf_t_crt(int moduli, int sym, int m, int nn, int k, const double* A, const double* B,
+             double alpha, const double* D, double beta, double gamma, double* C,
+             double* norm_sq, void* stream) {
+  return t_gemm_impl(-2, moduli, sym, m, nn, k, A, B, alpha, D, beta, gamma, C, norm_sq, stream);
 }
 
 int zf_t_ozaki(int slices, int sym, int m, int nn, int k, const double* A, const double* B,

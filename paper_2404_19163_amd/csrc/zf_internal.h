@@ -164,6 +164,24 @@ hipError_t launch_gemm_oz(const signed char* A, const int* ea, const signed char
 int oz_tile_edge(int np, bool sym);
 int oz_blocks(int np, bool sym);
 
+// FP64 products emulated through residues (crt.hip): rows scaled by 2^(beta - e_i)
+// and truncated to integers, the exact integer product recovered from one int8
+// product per modulus (L pairwise coprime moduli <= 256) by the Chinese remainder
+// theorem.  beta depends on L and on K, the number of valid (unpadded) terms of the
+// contraction.  Residue planes: L planes of np x np signed bytes (plane stride np^2)
+// and a per-row exponent.  The product runs the EpiParams epilogue on C = A B^T; its
+// norm partials number crt_blocks(np, sym).  np % 256 == 0, np <= kCrtMaxOrder;
+// rho is scratch for L byte planes.
+constexpr int kCrtMaxModuli = 15;
+constexpr int kCrtMaxOrder = 16384;
+int crt_beta(int L, long long K);  // -1 for an unsupported L
+hipError_t launch_crt_residues(const double* M, int np, int L, long long K, signed char* out,
+                               int* ex, hipStream_t st);
+hipError_t launch_crt_product(const signed char* A, const int* ea, const signed char* B,
+                              const int* eb, int np, int L, long long K, bool sym,
+                              unsigned char* rho, const EpiParams& ep, hipStream_t st);
+int crt_blocks(int np, bool sym);
+
 // Elementwise / reduction kernels (elementwise.hip)
 hipError_t launch_split_pad(const double* src, int n, int ld_src, int np, u16* hi, u16* lo,
                             double* copy64, float* copy32, bool transpose_copy, int fmt,

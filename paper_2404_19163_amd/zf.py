@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libzf.so")
 FP64, BF16X3, FP16X3, BF16, FP32, FP16 = 0, 1, 2, 3, 4, 5
 STOP_RATIO, STOP_MONOTONE = 0, 1
 REFINE_OFF, REFINE_F64_DELTA, REFINE_F64_FULL, REFINE_F32, REFINE_EMU = 0, 1, 2, 3, 4
+REFINE_CRT, REFINE_CRT_FIRST = 5, 6
 WARN_MAXSWEEPS, WARN_Z0_FALLBACK, WARN_HIST_TRUNC = 1, 2, 4
 Z0_GIVEN, Z0_SCALED_IDENTITY, Z0_LEARNED = 0, 1, 2
 ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NONFINITE, ERR_NOT_CONVERGED = -1, -2, -3, -4, -5
@@ -30,10 +31,10 @@ _PREC = {"fp64": FP64, "bf16x3": BF16X3, "fp16x3": FP16X3, "bf16": BF16, "fp32":
 _STOP = {"ratio": STOP_RATIO, "monotone": STOP_MONOTONE}
 _GUESS = {"identity": Z0_SCALED_IDENTITY, "learned": Z0_LEARNED, "given": Z0_GIVEN}
 _REFINE = {"off": REFINE_OFF, "f64_delta": REFINE_F64_DELTA, "f64_full": REFINE_F64_FULL,
-           "f32": REFINE_F32, "emu": REFINE_EMU}
+           "f32": REFINE_F32, "emu": REFINE_EMU, "crt": REFINE_CRT, "crt_first": REFINE_CRT_FIRST}
 KERNEL_CLASSES = ("gemm_x3", "gemm_x3_sym", "gemm_f64", "gemm_f64_sym", "gemm_hh", "gemm_hh_sym",
                   "gemm_f32", "gemm_f32_sym", "gemm_x3f16", "gemm_x3f16_sym", "gemm_hhf16",
-                  "gemm_hhf16_sym", "gemm_oz", "gemm_oz_sym")
+                  "gemm_hhf16_sym", "gemm_oz", "gemm_oz_sym", "gemm_crt", "gemm_crt_sym")
 
 
 class ZFError(RuntimeError):
@@ -63,7 +64,8 @@ EXPORTS = ("zf_default_opts", "zf_refine", "zf_refine_ex", "zf_residual", "zf_re
            "zf_batched_use_graph", "zf_batched_set_graph_sweeps", "zf_batched_last_stats",
            "zf_batched_release", "zf_features", "zf_guess_label",
            "zf_mlp_set_params", "zf_mlp_get_params", "zf_mlp_set_norm", "zf_mlp_train_step",
-           "zf_mlp_grad", "zf_mlp_predict", "zf_mlp_save", "zf_mlp_load", "zf_congruence", "zf_t_ozaki")
+           "zf_mlp_grad", "zf_mlp_predict", "zf_mlp_save", "zf_mlp_load", "zf_congruence", "zf_t_ozaki",
+           "zf_t_crt")
 N_PARAMS = 4931
 
 _lib = None
@@ -103,6 +105,8 @@ def lib() -> ctypes.CDLL:
     L.zf_t_gemm.restype = i
     L.zf_t_ozaki.argtypes = [i, i, i, i, i, vp, vp, d, vp, d, d, vp, P(d), vp]
     L.zf_t_ozaki.restype = i
+    L.zf_t_crt.argtypes = [i, i, i, i, i, vp, vp, d, vp, d, d, vp, P(d), vp]
+    L.zf_t_crt.restype = i
     L.zf_t_gershgorin.argtypes = [vp, i, P(d), vp]
     L.zf_t_gershgorin.restype = i
     L.zf_profile_enable.argtypes = [i]
@@ -373,7 +377,8 @@ def t_gemm(precision: str, A: torch.Tensor, B: torch.Tensor, *, sym: bool = Fals
            alpha: float = 0.0, D: torch.Tensor | None = None, beta: float = 1.0,
            gamma: float = 0.0, stream=None, slices: int = 0):
     """C = alpha D + beta A B^T + gamma I through one library GEMM; returns (C, sum C^2).
-    precision "emu" runs the emulated FP64 product with `slices` integer slices."""
+    precision "emu" runs the emulated FP64 product with `slices` integer slices, "crt"
+    the residue-emulated product with `slices` moduli."""
     m, k = A.shape
     nn = B.shape[0]
     for t, nm in ((A, "A"), (B, "B")):
@@ -387,9 +392,10 @@ def t_gemm(precision: str, A: torch.Tensor, B: torch.Tensor, *, sym: bool = Fals
     C = torch.empty((m, nn), dtype=torch.float64, device=A.device)
     nrm = ctypes.c_double(0.0)
     dptr = D.data_ptr() if D is not None else None
-    if precision == "emu":
-        rc = lib().zf_t_ozaki(slices, 1 if sym else 0, m, nn, k, A.data_ptr(), B.data_ptr(), alpha,
-                              dptr, beta, gamma, C.data_ptr(), ctypes.byref(nrm), _stream(stream))
+    if precision in ("emu", "crt"):
+        fn = lib().zf_t_ozaki if precision == "emu" else lib().zf_t_crt
+        rc = fn(slices, 1 if sym else 0, m, nn, k, A.data_ptr(), B.data_ptr(), alpha,
+                dptr, beta, gamma, C.data_ptr(), ctypes.byref(nrm), _stream(stream))
     else:
         rc = lib().zf_t_gemm(_PREC[precision], 1 if sym else 0, m, nn, k, A.data_ptr(),
                              B.data_ptr(), alpha, dptr, beta, gamma, C.data_ptr(),
