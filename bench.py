@@ -2,13 +2,16 @@
 """Benchmark of the refinement hot path on one MI355X.
 
 One step = one complete zf_refine call on one synthetic overlap matrix: setup
-(split, Z0), every low-precision sweep, the FP64 refinement phase with its
-residual evaluations, and the copy-out of Z.  Inputs are resident in HBM before
-the timed region starts.
+(split, Z0), every low-precision sweep, the refinement phase with its residual
+evaluations, and the copy-out of Z.  Inputs are resident in HBM before the timed
+region starts.  The headline refinement (--refine, default crt_first) takes its
+first residual from FP64 products emulated through residues on the int8 matrix
+cores and every later one, the stopping norm and the final residual included, in
+FP64; the other modes are timed beside it (refine_modes).
 
 Reported (one JSON line):
-  value        refined-Z TFLOP/s of the mixed path (BF16x3 sweeps + FP64
-               refinement) on the N = 4096 overlap: the method's irreducible
+  value        refined-Z TFLOP/s of the mixed path (BF16x3 sweeps + the
+               refinement phase) on the N = 4096 overlap: the method's irreducible
                flops / time, where one residual evaluation counts 3 N^3 (S Z and
                the symmetric Z^T (S Z)) and one update of order m counts
                (m + 1) N^3 (m - 1 symmetric delta products and Z Q);
@@ -84,6 +87,19 @@ WORKLOADS = {
 }
 
 
+REFINE_DESC = {
+    "crt_first": "refinement phase (Algorithm 3): first residual from FP64 products emulated "
+                 "through residues on the int8 matrix cores, the stopping norm and the final "
+                 "residual in FP64, BF16x3 corrections",
+    "f64_delta": "refinement phase (Algorithm 3): FP64 residuals, BF16x3 corrections",
+    "crt": "refinement phase (Algorithm 3): every residual from FP64 products emulated through "
+           "residues, BF16x3 corrections",
+    "emu": "refinement phase (Algorithm 3): every residual from FP64 products emulated with "
+           "integer slices, BF16x3 corrections",
+    "f64_full": "refinement phase (Algorithm 3): FP64 residuals and FP64 corrections",
+}
+
+
 def alg_flops(n: int, order: int, evals: int, updates: int) -> float:
     """The method's irreducible flops: a residual evaluation is S Z (2 N^3) plus the
     symmetric Z^T (S Z) (N^3); an update of order m is m - 1 symmetric delta products
@@ -106,7 +122,10 @@ def kernel_alg_flops(cls: str, n: int) -> float:
             "gemm_hh": 2 * n ** 3, "gemm_hh_sym": n * n * (n + 1),
             "gemm_f32": 2 * n ** 3, "gemm_f32_sym": n * n * (n + 1),
             "gemm_x3f16": 6 * n ** 3, "gemm_x3f16_sym": 3 * n * n * (n + 1),
-            "gemm_hhf16": 2 * n ** 3, "gemm_hhf16_sym": n * n * (n + 1)}.get(cls, 0.0)
+            "gemm_hhf16": 2 * n ** 3, "gemm_hhf16_sym": n * n * (n + 1),
+            # emulated FP64 products: the FP64 flops they stand for
+            "gemm_crt": 2 * n ** 3, "gemm_crt_sym": n * n * (n + 1),
+            "gemm_oz": 2 * n ** 3, "gemm_oz_sym": n * n * (n + 1)}.get(cls, 0.0)
 
 
 def timed_solves(fn, steps: int, warmup: int):
@@ -182,7 +201,8 @@ def cpu_oracle_baseline(S_np, order: int, evals: int, updates: int, gpu_s: float
             "time_ratio_vs_gpu_1thread": round(est * t_eval1 / t_eval / gpu_s, 1)}
 
 
-def run_single(args, name: str, S_np, with_profile: bool, legs=("fp64", "emu", "crt")) -> dict:
+def run_single(args, name: str, S_np, with_profile: bool,
+               legs=("fp64", "f64_delta", "emu", "crt")) -> dict:
     """Mixed (headline) and FP64 legs of zf_refine on one matrix, with per-kernel
     times, roofline fractions and oracle checks."""
     import torch
@@ -196,7 +216,7 @@ def run_single(args, name: str, S_np, with_profile: bool, legs=("fp64", "emu", "
     stream = torch.cuda.current_stream()
 
     def run(precision, out, refine=None):
-        refine = refine or getattr(args, "refine", "f64_delta")
+        refine = refine or getattr(args, "refine", "crt_first")
         return zf.refine(S, None, order=args.order, precision=precision, out=out, stream=stream,
                          refine=refine)
 
@@ -237,28 +257,26 @@ def run_single(args, name: str, S_np, with_profile: bool, legs=("fp64", "emu", "
         res["Zd"] = Zd
         print(f"[bench] {name} fp64: {fp64_s * 1e3:.3f} ms/step iters={r64.iters} "
               f"rms={r64.final_rms:.3e}", file=sys.stderr, flush=True)
-    if "emu" in legs and args.fp64_steps > 0 and n <= 16384:
-        Ze = torch.empty_like(S)
-        emu_s, re_ = timed_solves(lambda: run("bf16x3", Ze, "emu"), args.fp64_steps, 1)
-        res["emu"] = {"ms": round(emu_s * 1e3, 3), "evals": [re_.low_evals, re_.high_evals],
-                      "final_rms": re_.final_rms,
-                      "slices": int(os.environ.get("ZF_EMU_SLICES", "7")),
-                      "fp64_rms": zf.residual(S, Ze)}
-        print(f"[bench] {name} mixed, emulated FP64 residual: {emu_s * 1e3:.3f} ms/step "
-              f"rms={re_.final_rms:.3e}", file=sys.stderr, flush=True)
-
-    for mode in ("crt_first", "crt"):
-        if "crt" not in legs or args.fp64_steps <= 0 or n > 16384:
-            break
-        Zc = torch.empty_like(S)
-        crt_s, rc_ = timed_solves(lambda: run("bf16x3", Zc, mode), max(args.fp64_steps, 5), 1)
-        res[mode] = {"ms": round(crt_s * 1e3, 3), "evals": [rc_.low_evals, rc_.high_evals],
-                     "final_rms": rc_.final_rms,
-                     "moduli": int(os.environ.get("ZF_EMU_MODULI", "14")),
-                     "fp64_rms": zf.residual(S, Zc),
-                     "speedup_vs_fp64_residual": round(mixed_s / crt_s, 3)}
-        print(f"[bench] {name} mixed, residue-emulated residual ({mode}): {crt_s * 1e3:.3f} ms/step "
-              f"rms={rc_.final_rms:.3e}", file=sys.stderr, flush=True)
+    # the other refinement modes of the mixed path, each timed without events
+    head = getattr(args, "refine", "crt_first")
+    other = {"f64_delta": "fp64 residual", "crt_first": "residue-emulated first residual",
+             "crt": "residue-emulated residuals", "emu": "slice-emulated residuals"}
+    for mode, what in other.items():
+        if mode == head or args.fp64_steps <= 0 or (mode != "f64_delta" and n > 16384):
+            continue
+        if mode not in legs and not (mode in ("crt_first", "crt") and "crt" in legs):
+            continue
+        Zo = torch.empty_like(S)
+        o_s, ro = timed_solves(lambda: run("bf16x3", Zo, mode), max(args.fp64_steps, 5), 1)
+        res[mode] = {"ms": round(o_s * 1e3, 3), "evals": [ro.low_evals, ro.high_evals],
+                     "final_rms": ro.final_rms, "fp64_rms": zf.residual(S, Zo),
+                     "headline_speedup_over_this": round(o_s / noev_s, 3)}
+        if mode == "emu":
+            res[mode]["slices"] = int(os.environ.get("ZF_EMU_SLICES", "7"))
+        if mode.startswith("crt"):
+            res[mode]["moduli"] = int(os.environ.get("ZF_EMU_MODULI", "14"))
+        print(f"[bench] {name} mixed, {what}: {o_s * 1e3:.3f} ms/step rms={ro.final_rms:.3e}",
+              file=sys.stderr, flush=True)
 
     # residuals and distances checked by the CPU oracle
     Zm_np = Zm.cpu().numpy()
@@ -335,7 +353,7 @@ def main() -> int:
     ap.add_argument("--headline-only", action="store_true",
                     help="only the N=4096 workload (skip the other configurations)")
     ap.add_argument("--mixed-only", action="store_true", help="skip the FP64 path (profiling runs)")
-    ap.add_argument("--refine", default="f64_delta",
+    ap.add_argument("--refine", default="crt_first",
                     choices=["f64_delta", "crt_first", "crt", "emu", "f64_full"],
                     help="refinement mode of the headline mixed path")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -413,7 +431,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": n, "seed": args.seed, "order": args.order,
                    "z0": "scaled identity", "stop": "ratio (Algorithm 2)",
-                   "refine": "FP64 residual + BF16x3 correction"},
+                   "refine": REFINE_DESC[args.refine]},
         "flop_basis": "irreducible: 3 N^3 per residual evaluation (S Z and the symmetric "
                       "Z^T (S Z)), (m + 1) N^3 per update (6 N^3 per order-2 sweep); "
                       "tflops_paper_count uses 4 N^3 + 2 m N^3 (every product dense)",
@@ -427,9 +445,7 @@ def main() -> int:
         "fp64": fp64,
         # both legs timed without per-GEMM events
         "speedup_vs_fp64": round(fp64["ms"] / mixed["ms_without_events"], 3) if fp64 else None,
-        "mixed_emulated_residual": r.get("emu"),
-        "mixed_crt_first_residual": r.get("crt_first"),
-        "mixed_crt_residual": r.get("crt"),
+        "refine_modes": {m: r[m] for m in ("f64_delta", "crt_first", "crt", "emu") if m in r},
         "checks": r["checks"],
         "kernels": kernel_table(prof, n, total_s),
         "roofline": roofline(prof, n, total_s),
@@ -472,9 +488,10 @@ def other_configs(args) -> dict:
     S_np = inputs.workload("cluster5049", args.seed)
     sub = argparse.Namespace(**vars(args))
     sub.steps, sub.warmup, sub.fp64_steps = 5, 2, 2
-    r = run_single(sub, "cluster5049", S_np, with_profile=False, legs=("fp64", "crt"))
+    r = run_single(sub, "cluster5049", S_np, with_profile=False, legs=("fp64", "f64_delta", "crt"))
     c3 = {"workload": WORKLOADS["cluster5049"]["desc"], "mixed": r["mixed"], "fp64": r.get("fp64"),
-          "crt_first": r.get("crt_first"), "crt": r.get("crt"), "checks": r["checks"]}
+          "refine_modes": {m: r[m] for m in ("f64_delta", "crt_first", "crt") if m in r},
+          "checks": r["checks"]}
     if r.get("fp64"):
         c3["speedup_vs_fp64"] = round(r["fp64"]["ms"] / r["mixed"]["ms"], 3)
     out["cluster5049"] = c3

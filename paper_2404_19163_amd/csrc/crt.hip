@@ -31,6 +31,13 @@ namespace zf {
 constexpr int kCrtBad = INT_MIN;
 constexpr int kCrtLimbBits = 41;
 
+// The moduli, largest first (pairwise coprime, each <= 256); the first L are used.
+__host__ __device__ constexpr int crt_mod(int l) {
+  constexpr int m[kCrtMaxModuli] = {256, 255, 253, 251, 247, 241, 239, 233,
+                                    229, 227, 223, 217, 211, 199, 197};
+  return m[l];
+}
+
 // Constants of one moduli set, passed by value to the kernels.
 struct CrtConsts {
   int L, beta;
@@ -46,8 +53,9 @@ struct CrtConsts {
 // One block per row: the row's largest magnitude and exponent, then for 4
 // consecutive columns per thread the integer a = trunc(x 2^(beta - e)) (|a| < 2^52,
 // exact) and its balanced residue modulo each m_l (one 4-byte store per plane).
+template <int L>
 __global__ void __launch_bounds__(256) crt_residue_kernel(const double* __restrict__ Mat, int np,
-                                                          size_t plane, CrtConsts cc,
+                                                          size_t plane, int beta,
                                                           signed char* __restrict__ out,
                                                           int* __restrict__ ex) {
   __shared__ double red[4];
@@ -79,9 +87,10 @@ __global__ void __launch_bounds__(256) crt_residue_kernel(const double* __restri
   for (int k0 = threadIdx.x * 4; k0 < np; k0 += 1024) {
     double a[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = bad ? 0.0 : trunc(ldexp(r[k0 + q], cc.beta - e));
-    for (int l = 0; l < cc.L; ++l) {
-      const int md = cc.mod[l];
+    for (int q = 0; q < 4; ++q) a[q] = bad ? 0.0 : trunc(ldexp(r[k0 + q], beta - e));
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int md = crt_mod(l);
       const double dm = (double)md, inv = 1.0 / dm;
       unsigned packed = 0;
 #pragma unroll
@@ -233,9 +242,6 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-static const int kCrtModuli[kCrtMaxModuli] = {256, 255, 253, 251, 247, 241, 239, 233,
-                                              229, 227, 223, 217, 211, 199, 197};
-
 typedef unsigned __int128 u128;
 
 static long long inv_mod(long long a, long long m) {  // a^-1 mod m, gcd(a, m) = 1
@@ -256,14 +262,14 @@ static long long inv_mod(long long a, long long m) {  // a^-1 mod m, gcd(a, m) =
 static bool crt_consts(int L, long long K, CrtConsts& cc) {
   if (L < 2 || L > kCrtMaxModuli || K < 1) return false;
   u128 M = 1;
-  for (int l = 0; l < L; ++l) M *= (u128)kCrtModuli[l];
+  for (int l = 0; l < L; ++l) M *= (u128)crt_mod(l);
   cc.L = L;
   int b = 0;  // largest beta with 4 K 4^beta <= M
   while (b < 52 && ((u128)4 * (u128)K << (2 * (b + 1))) <= M) ++b;
   cc.beta = b;
   const u128 mask = ((u128)1 << kCrtLimbBits) - 1;
   for (int l = 0; l < L; ++l) {
-    const long long m = kCrtModuli[l];
+    const long long m = crt_mod(l);
     cc.mod[l] = (int)m;
     const u128 Ml = M / (u128)m;
     const u128 w = Ml * (u128)inv_mod((long long)(Ml % (u128)m), m) % M;
@@ -290,8 +296,20 @@ hipError_t launch_crt_residues(const double* Mat, int np, int L, long long K, si
                                int* ex, hipStream_t st) {
   CrtConsts cc;
   if (np <= 0 || np % 256 != 0 || !crt_consts(L, K, cc)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(crt_residue_kernel, dim3(np), dim3(256), 0, st, Mat, np, (size_t)np * np, cc,
-                     out, ex);
+  const size_t plane = (size_t)np * np;
+#define ZF_CRT_RES(LL)                                                                        \
+  case LL:                                                                                     \
+    hipLaunchKernelGGL(crt_residue_kernel<LL>, dim3(np), dim3(256), 0, st, Mat, np, plane,     \
+                       cc.beta, out, ex);                                                      \
+    break;
+  switch (L) {
+    ZF_CRT_RES(2) ZF_CRT_RES(3) ZF_CRT_RES(4) ZF_CRT_RES(5) ZF_CRT_RES(6) ZF_CRT_RES(7)
+    ZF_CRT_RES(8) ZF_CRT_RES(9) ZF_CRT_RES(10) ZF_CRT_RES(11) ZF_CRT_RES(12) ZF_CRT_RES(13)
+    ZF_CRT_RES(14) ZF_CRT_RES(15)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef ZF_CRT_RES
   return hipGetLastError();
 }
 
