@@ -8,8 +8,11 @@
 //   L2  grouped BF16x3 GEMM  delta = I - Z^T A     (symmetric, norm partials)
 //   H1  grouped FP64 GEMM    A^T = Z^T S           (matrices in the FP64 phase)
 //   H2  grouped FP64 GEMM    delta = I - Z^T A     (symmetric, norm partials)
-//   DECIDE  per matrix: Err, history, stop test, next action (device-side)
-//   WIDEN   FP32 -> FP64 Z for matrices that just left the low phase
+//   DECIDE  per matrix: Err, history, stop test, next action (device-side); a
+//           matrix whose low phase stops waits (parked) until every low phase has
+//           stopped, then all enter the FP64 phase together, so that the FP64
+//           stages run once per macro-sweep with every matrix in them
+//   WIDEN   FP32 -> FP64 Z for matrices that just entered the FP64 phase
 //   U3  grouped BF16x3 GEMM  Q = c1 delta + c2 delta^2  (matrices updating)
 //   U4  grouped BF16x3 GEMM  Z_new = Z + Z Q           (matrices updating)
 //
@@ -54,7 +57,9 @@ namespace zf {
   } while (0)
 
 enum { PH_LOW = 0, PH_HIGH = 1 };
-enum { ACT_EVAL = 0, ACT_UPDATE = 1, ACT_TRANSITION = 2, ACT_DONE = 3 };
+// ACT_PARKED: the low phase has stopped and the FP64 phase waits for every other
+// matrix's low phase to stop, so that the FP64 stages run with all matrices at once.
+enum { ACT_EVAL = 0, ACT_UPDATE = 1, ACT_TRANSITION = 2, ACT_DONE = 3, ACT_PARKED = 4 };
 enum { OP_L1 = 0, OP_L2, OP_H1, OP_H2, OP_U3, OP_U4, OP_S2 };
 
 // Per-matrix record: buffers (carved from one arena) and the device-side state of
@@ -93,7 +98,7 @@ __device__ __forceinline__ bool op_applies(int op, const BMat& M) {
       return M.learn != 0;
     case OP_L1:
     case OP_L2:
-      return phase == PH_LOW && action != ACT_DONE;
+      return phase == PH_LOW && action != ACT_DONE && action != ACT_PARKED;
     case OP_H1:
     case OP_H2:
       return phase == PH_HIGH && action != ACT_DONE;
@@ -256,12 +261,19 @@ __global__ void decide_kernel(BMat* mats, int count, const double* __restrict__ 
                               int* remaining) {
   // remaining[0]: matrices not yet done; remaining[1]: macro-sweeps that had any
   if (remaining[0] == 0) return;
-  __shared__ int live;
-  if (threadIdx.x == 0) live = 0;
+  __shared__ int live, low_running;
+  if (threadIdx.x == 0) {
+    live = 0;
+    low_running = 0;
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < count; i += blockDim.x) {
     BMat& M = mats[i];
     if (M.action == ACT_DONE) continue;
+    if (M.action == ACT_PARKED) {  // not evaluated: waiting for the other low phases
+      atomicAdd(&live, 1);
+      continue;
+    }
     // every matrix not yet done was evaluated in this macro-sweep
     double s = 0.0;
     const int parts = (M.phase == PH_HIGH) ? M.ftiles_sym : M.tiles_sym;  // phase just evaluated
@@ -299,9 +311,7 @@ __global__ void decide_kernel(BMat* mats, int count, const double* __restrict__ 
         M.upd_l = upd;
         M.err_l = chosen;
         if (refine_on) {
-          M.phase = PH_HIGH;
-          M.it = 0;
-          M.action = ACT_TRANSITION;
+          M.action = ACT_PARKED;
         } else {
           M.action = ACT_DONE;
         }
@@ -318,8 +328,20 @@ __global__ void decide_kernel(BMat* mats, int count, const double* __restrict__ 
       M.action = ACT_UPDATE;
     }
     if (M.action != ACT_DONE) atomicAdd(&live, 1);
+    if (M.phase == PH_LOW && M.action != ACT_DONE && M.action != ACT_PARKED)
+      atomicAdd(&low_running, 1);
   }
   __syncthreads();
+  // once no low phase is running, every parked matrix enters the FP64 phase together
+  if (low_running == 0) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+      BMat& M = mats[i];
+      if (M.action != ACT_PARKED) continue;
+      M.phase = PH_HIGH;
+      M.it = 0;
+      M.action = ACT_TRANSITION;
+    }
+  }
   if (threadIdx.x == 0) {
     remaining[0] = live;
     remaining[1] += 1;
