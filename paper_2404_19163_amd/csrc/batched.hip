@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(X3G<T>::NT, 2)
   using CF = X3G<T>;
   __shared__ __attribute__((aligned(16))) u16 lds[2 * CF::STAGE_ELEMS];
   __shared__ double red[CF::NT / 64];
-  if (live && *live == 0) return;  // every matrix has stopped
+  if (live && *live == 0) return;  // no matrix in this stage
   int t0, t1, step;
   xcd_run(seg, T == 128 ? 0 : 1, t0, t1, step);
   for (int t = t0; t < t1; t += step) {
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(256, 4)
                        const int* __restrict__ live) {
   __shared__ double lds[2 * F64_64::STAGE];
   __shared__ double red[4];
-  if (*live == 0) return;  // every matrix has stopped
+  if (*live == 0) return;  // no matrix in this stage
   int t0, t1, step;
   xcd_run(seg, 1, t0, t1, step);
   for (int t = t0; t < t1; t += step) {
@@ -259,12 +259,18 @@ __global__ void __launch_bounds__(256, 4)
 __global__ void decide_kernel(BMat* mats, int count, const double* __restrict__ partials, int order,
                               int rule, int max_l, int max_h, int refine_on, int hist_cap,
                               int* remaining) {
-  // remaining[0]: matrices not yet done; remaining[1]: macro-sweeps that had any
+  // remaining[0]: matrices not yet done; remaining[1]: macro-sweeps that had any;
+  // the matrices each stage will find: [2] low-phase evaluations of the next
+  // macro-sweep, [3] FP64 evaluations of the next macro-sweep, [4] updates of this
+  // macro-sweep, [5] widenings of this macro-sweep (each stage returns at once on 0)
   if (remaining[0] == 0) return;
-  __shared__ int live, low_running;
+  __shared__ int live, low_running, n_high, n_upd, n_trans;
   if (threadIdx.x == 0) {
     live = 0;
     low_running = 0;
+    n_high = 0;
+    n_upd = 0;
+    n_trans = 0;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < count; i += blockDim.x) {
@@ -330,6 +336,8 @@ __global__ void decide_kernel(BMat* mats, int count, const double* __restrict__ 
     if (M.action != ACT_DONE) atomicAdd(&live, 1);
     if (M.phase == PH_LOW && M.action != ACT_DONE && M.action != ACT_PARKED)
       atomicAdd(&low_running, 1);
+    if (M.phase == PH_HIGH && M.action != ACT_DONE) atomicAdd(&n_high, 1);
+    if (M.action == ACT_UPDATE) atomicAdd(&n_upd, 1);
   }
   __syncthreads();
   // once no low phase is running, every parked matrix enters the FP64 phase together
@@ -340,19 +348,31 @@ __global__ void decide_kernel(BMat* mats, int count, const double* __restrict__ 
       M.phase = PH_HIGH;
       M.it = 0;
       M.action = ACT_TRANSITION;
+      atomicAdd(&n_high, 1);
+      atomicAdd(&n_trans, 1);
     }
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     remaining[0] = live;
     remaining[1] += 1;
+    remaining[2] = low_running;
+    remaining[3] = n_high;
+    remaining[4] = n_upd;
+    remaining[5] = n_trans;
   }
 }
 
-// remaining[0] = count (every matrix live), remaining[1] = 0 macro-sweeps
+// remaining[0] = count (every matrix live), remaining[1] = 0 macro-sweeps, every
+// matrix starting in the low phase, no update, FP64 evaluation or widening pending
 __global__ void b_reset_kernel(int* remaining, int count) {
   if (threadIdx.x == 0) {
     remaining[0] = count;
     remaining[1] = 0;
+    remaining[2] = count;
+    remaining[3] = 0;
+    remaining[4] = 0;
+    remaining[5] = 0;
   }
 }
 
@@ -786,22 +806,27 @@ static void x3_group(const TileTask* tasks, const int* seg, const int* hseg, con
 
 // one macro-sweep on stream st (captured into the graph, or run eagerly)
 static hipError_t macro_sweep(const Launch& L, hipStream_t st) {
-  const int* live = L.remaining;
-  x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_L1, 0.0, 0.0, L.partials, L.grid, st, live);
-  x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_L2, 0.0, 0.0, L.partials, L.grid, st, live);
+  // each stage reads the count of matrices it will find (written by DECIDE) and
+  // returns at once when it is zero
+  const int* low = L.remaining + 2;
+  const int* high = L.remaining + 3;
+  const int* upd = L.remaining + 4;
+  const int* trans = L.remaining + 5;
+  x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_L1, 0.0, 0.0, L.partials, L.grid, st, low);
+  x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_L2, 0.0, 0.0, L.partials, L.grid, st, low);
   if (L.refine_on) {
     // 64-wide FP64 tiles fit four blocks per CU: twice the grid
     hipLaunchKernelGGL(grouped_f64_kernel, dim3(2 * L.grid), dim3(256), 0, st, L.ffull, L.ffseg,
-                       L.mats, (int)OP_H1, L.partials, live);
+                       L.mats, (int)OP_H1, L.partials, high);
     hipLaunchKernelGGL(grouped_f64_kernel, dim3(2 * L.grid), dim3(256), 0, st, L.fsym, L.fsseg,
-                       L.mats, (int)OP_H2, L.partials, live);
+                       L.mats, (int)OP_H2, L.partials, high);
   }
   hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, st, L.mats, L.count, L.partials, L.order,
                      L.rule, L.max_l, L.max_h, L.refine_on, L.hist_cap, L.remaining);
   if (L.refine_on)
-    hipLaunchKernelGGL(b_widen_kernel, dim3(L.etiles, L.count), dim3(256), 0, st, L.mats, live);
-  x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_U3, L.c1, L.c2, L.partials, L.grid, st, live);
-  x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_U4, 0.0, 0.0, L.partials, L.grid, st, live);
+    hipLaunchKernelGGL(b_widen_kernel, dim3(L.etiles, L.count), dim3(256), 0, st, L.mats, trans);
+  x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_U3, L.c1, L.c2, L.partials, L.grid, st, upd);
+  x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_U4, 0.0, 0.0, L.partials, L.grid, st, upd);
   return hipGetLastError();
 }
 
