@@ -586,27 +586,46 @@ __global__ void __launch_bounds__(256) b_init_kernel(const BMat* __restrict__ ma
   }
 }
 
-// FP32 master -> FP64 row-major and transposed for matrices entering the FP64 phase
-__global__ void __launch_bounds__(256) b_widen_kernel(const BMat* __restrict__ mats,
-                                                      const int* __restrict__ live) {
+// FP32 master -> FP64 row-major and transposed for matrices entering the FP64 phase.
+// It runs in every macro-sweep but has work in one, so it is a fixed grid walking the
+// (matrix, 64 x 64 tile) pairs with a stride rather than a grid of every pair: the
+// launches without work cost one read of the count.
+__global__ void __launch_bounds__(256) b_widen_kernel(const BMat* __restrict__ mats, int count,
+                                                      int etiles, const int* __restrict__ live) {
   __shared__ float tv[kET][kET + 1];
   if (*live == 0) return;
-  const BMat& M = mats[blockIdx.y];
-  if (M.action != ACT_TRANSITION) return;
-  int i0, j0;
-  if (!tile_of(M, i0, j0)) return;
-  const int np = M.np, cur = M.cur;
-  for (int e = threadIdx.x; e < kET * kET; e += 256) {
-    const int r = e / kET, c = e % kET;
-    const size_t le = (size_t)(i0 + r) * np + j0 + c;
-    const float f = M.z32[cur][le];
-    M.z64r[cur][le] = (double)f;
-    tv[r][c] = f;
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kET * kET; e += 256) {
-    const int r = e / kET, c = e % kET;
-    M.z64c[cur][(size_t)(j0 + r) * np + i0 + c] = (double)tv[c][r];
+  const long long total = (long long)count * etiles;
+  for (long long w = blockIdx.x; w < total; w += gridDim.x) {
+    const int m = (int)(w / etiles), et = (int)(w - (long long)m * etiles);
+    const BMat& M = mats[m];
+    if (M.action != ACT_TRANSITION) continue;  // uniform over the block
+    const int T = M.np / kET;
+    if (et >= T * T) continue;
+    const int i0 = (et / T) * kET, j0 = (et % T) * kET;
+    const int np = M.np, cur = M.cur;
+    const float* __restrict__ src = M.z32[cur];
+    double* __restrict__ dr = M.z64r[cur];
+    double* __restrict__ dc = M.z64c[cur];
+    constexpr int PER = kET * kET / 256;
+    float f[PER];  // every load of the tile requested before any store
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + 256 * q, r = e / kET, c = e % kET;
+      f[q] = src[(size_t)(i0 + r) * np + j0 + c];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + 256 * q, r = e / kET, c = e % kET;
+      dr[(size_t)(i0 + r) * np + j0 + c] = (double)f[q];
+      tv[r][c] = f[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + 256 * q, r = e / kET, c = e % kET;
+      dc[(size_t)(j0 + r) * np + i0 + c] = (double)tv[c][r];
+    }
+    __syncthreads();  // tv is rewritten by the next pair
   }
 }
 
@@ -824,7 +843,8 @@ static hipError_t macro_sweep(const Launch& L, hipStream_t st) {
   hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, st, L.mats, L.count, L.partials, L.order,
                      L.rule, L.max_l, L.max_h, L.refine_on, L.hist_cap, L.remaining);
   if (L.refine_on)
-    hipLaunchKernelGGL(b_widen_kernel, dim3(L.etiles, L.count), dim3(256), 0, st, L.mats, trans);
+    hipLaunchKernelGGL(b_widen_kernel, dim3(8 * L.grid), dim3(256), 0, st, L.mats, L.count,
+                       L.etiles, trans);
   x3_group(L.sym, L.sseg, L.hsseg, L.mats, OP_U3, L.c1, L.c2, L.partials, L.grid, st, upd);
   x3_group(L.full, L.fseg, L.hfseg, L.mats, OP_U4, 0.0, 0.0, L.partials, L.grid, st, upd);
   return hipGetLastError();
