@@ -111,7 +111,8 @@ hipError_t launch_row_abs_max(const double* S, int n, int ld, double* row_sums, 
 }
 
 // ---------------------------------------------------------------------------
-// Z0 = I / sqrt(g) in every layout the sweep reads (g read on the device).
+// Z0 = I / sqrt(g) in every layout the sweep reads (g read on the device).  The
+// transposed pair zc is K-blocked (kb_offset); the loop walks it in storage order.
 // ---------------------------------------------------------------------------
 __global__ void init_identity_kernel(const double* __restrict__ g, int n, int np, float* z32,
                                      double* z64r, double* z64c, u16* zr_hi, u16* zr_lo,
@@ -129,7 +130,15 @@ __global__ void init_identity_kernel(const double* __restrict__ g, int n, int np
     if (z64r) z64r[e] = v;
     if (z64c) z64c[e] = v;
     if (zr_hi) { zr_hi[e] = h; zr_lo[e] = l; }
-    if (zc_hi) { zc_hi[e] = h; zc_lo[e] = l; }
+    if (zc_hi) {  // storage element e of the K-blocked zc: k block e / (32 np), row, k % 32
+      const size_t panel = (size_t)np << 5;
+      const int kk = (int)(e / panel) * 32 + (int)(e & 31), rr = (int)((e % panel) >> 5);
+      const float fc = (rr == kk && rr < n) ? (float)c : 0.0f;
+      u16 hc, lc;
+      split_bf16(fc, hc, lc);
+      zc_hi[e] = hc;
+      zc_lo[e] = lc;
+    }
   }
 }
 
@@ -142,10 +151,10 @@ hipError_t launch_init_identity(const double* g, int n, int np, float* z32, doub
   return hipGetLastError();
 }
 
-// Given Z0 (n x n, ld n): padded copies in row-major and transposed layouts.  One
-// 64 x 64 tile per block; the transposed copies go through a padded LDS tile so that
-// Z0 is read, and every layout written, in contiguous rows.  The pairs are the split
-// of Z0's FP32 value.
+// Given Z0 (n x n, ld n): padded copies in row-major and transposed layouts (the
+// transposed pair K-blocked, kb_offset).  One 64 x 64 tile per block; the transposed
+// copies go through a padded LDS tile so that Z0 is read, and every layout written,
+// in contiguous runs.  The pairs are the split of Z0's FP32 value.
 __global__ void __launch_bounds__(256) init_given_kernel(const double* __restrict__ Z0, int n,
                                                          int np, float* __restrict__ z32,
                                                          double* __restrict__ z64r,
@@ -181,8 +190,9 @@ __global__ void __launch_bounds__(256) init_given_kernel(const double* __restric
     if (zc_hi) {
       u16 h, l;
       split_bf16((float)v, h, l);
-      zc_hi[idx] = h;
-      zc_lo[idx] = l;
+      const size_t kidx = kb_offset(j0 + r, i0 + c, np);
+      zc_hi[kidx] = h;
+      zc_lo[kidx] = l;
     }
   }
 }
@@ -200,9 +210,10 @@ hipError_t launch_init_given(const double* Z0, int n, int np, float* z32, double
 // FP32 master -> FP64 row-major and transposed (start of the refinement phase).
 // FP32 matrix X (np x np, row-major) -> any of: FP64 row-major, FP64 transposed,
 // FP32 transposed, and 16-bit pairs (format fmt) of scale * X, row-major and/or
-// transposed.  scale is a power of two (exact).  One 64 x 64 tile per block; the
-// transposed copies go through a padded LDS tile so that both layouts are read
-// and written in contiguous rows.
+// transposed (the transposed pair K-blocked, kb_offset, as Z's transposed pair is).
+// scale is a power of two (exact).  One 64 x 64 tile per block; the transposed
+// copies go through a padded LDS tile so that both layouts are read and written in
+// contiguous runs.
 __global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ z32, int np,
                                                     double* __restrict__ z64r,
                                                     double* __restrict__ z64c,
@@ -235,8 +246,9 @@ __global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ z3
     if (pch) {
       u16 h, l;
       split_pair(v * scale, h, l, fmt);
-      pch[idx] = h;
-      pcl[idx] = l;
+      const size_t kidx = kb_offset(j0 + r, i0 + c, np);
+      pch[kidx] = h;
+      pcl[kidx] = l;
     }
   }
 }

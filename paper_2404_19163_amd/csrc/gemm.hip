@@ -4,7 +4,10 @@
 // (M x K) and B (N x K) row-major, i.e. both operands contiguous along the
 // contracted index.  The sweep keeps every operand in that form: S and the
 // iterates delta, Q are symmetric, and Z is stored both row-major and
-// transposed, so no kernel ever needs a transposing load.
+// transposed, so no kernel ever needs a transposing load.  Z's transposed pair
+// is K-blocked (kb_offset: 32-wide K blocks, each a row-major panel), which the
+// BF16x3 main loop reads through its per-operand K-block stride and which the
+// update's transposed epilogue writes as one contiguous run per strip.
 //
 //   gemm_x3  : (h)(h) + (h)(l) + (l)(h) of Sec. III.B (Eqs. SZn, Xn, Xsq): each
 //              operand is a BF16 hi/lo pair, the three products accumulate into
@@ -32,7 +35,7 @@ template <int BM, int BN, int BK, int WM, int WN, bool SYM, int PM, int NS>
 __global__ void __launch_bounds__(WM* WN * 64)
     gemm_x3_kernel(const u16* __restrict__ Ahi, const u16* __restrict__ Alo, int lda,
                    const u16* __restrict__ Bhi, const u16* __restrict__ Blo, int ldb, int K,
-                   int tiles_n, int gm, EpiParams ep) {
+                   int tiles_n, int gm, EpiParams ep, int ksa, int ksb) {
   using C = X3Cfg<BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) u16 lds[NS * C::STAGE_ELEMS];
   __shared__ double red[C::NT / 64];
@@ -41,7 +44,7 @@ __global__ void __launch_bounds__(WM* WN * 64)
   tile_coords(bid, tiles_n, SYM, ti, tj, gm);
   const int mode = SYM ? (ti == tj ? 2 : 1) : 0;
   x3_tile<BM, BN, BK, WM, WN, PM, NS>(Ahi, Alo, lda, Bhi, Blo, ldb, K, ti * BM, tj * BN, mode, ep,
-                                  tile_index(ti, tj, tiles_n, SYM), lds, red);
+                                  tile_index(ti, tj, tiles_n, SYM), lds, red, ksa, ksb);
 }
 
 // FP32 matrix-core GEMM ("single"): f32_mainloop + the shared epilogue.
@@ -151,14 +154,15 @@ int max_blocks(int M, int N) { return grid_blocks(M, N, 64, false); }
 template <int BM, int BN, int WM, int WN, int PM, int NS = 2>
 static void x3_launch(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                       int ldb, int M, int N, int K, bool sym, int blocks, const EpiParams& ep,
-                      hipStream_t st) {
+                      hipStream_t st, int ksa, int ksb) {
   if (sym)
     hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, true, PM, NS>), dim3(blocks),
-                       dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym_group(), ep);
+                       dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN, sym_group(), ep,
+                       ksa, ksb);
   else
     hipLaunchKernelGGL((gemm_x3_kernel<BM, BN, 32, WM, WN, false, PM, NS>), dim3(blocks),
                        dim3(WM * WN * 64), 0, st, Ahi, Alo, lda, Bhi, Blo, ldb, K, N / BN,
-                       tile_group(M, BM), ep);
+                       tile_group(M, BM), ep, ksa, ksb);
 }
 
 template <int BM, int BN, int WM, int WN>
@@ -187,33 +191,43 @@ static void f64_launch(const double* A, int lda, const double* B, int ldb, int M
 template <int PM>
 static void x3_dispatch(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                         int ldb, int M, int N, int K, bool sym, int tile, int blocks,
-                        const EpiParams& ep, hipStream_t st) {
+                        const EpiParams& ep, hipStream_t st, int ksa, int ksb) {
   if (tile == 256)
-    x3_launch<256, 256, 2, 4, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+    x3_launch<256, 256, 2, 4, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st, ksa,
+                                  ksb);
   else if (tile == 128)  // 8 waves of 32 x 64 and a 3-stage ring (loads two stages ahead)
-    x3_launch<128, 128, 4, 2, PM, 3>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+    x3_launch<128, 128, 4, 2, PM, 3>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st,
+                                     ksa, ksb);
   else
-    x3_launch<64, 64, 2, 2, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st);
+    x3_launch<64, 64, 2, 2, PM>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, blocks, ep, st, ksa,
+                                ksb);
 }
 
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
-                          hipStream_t st, int pm) {
+                          hipStream_t st, int pm, int ksa, int ksb) {
   if (!dims_ok(M, N, K, sym) || pm < 0 || pm > 3) return hipErrorInvalidValue;
+  // a K-blocked transposed output holds only 16-bit pairs; ks is 32 or a multiple of it
+  if (ep.t_kb && (ep.ot32 || ep.ot64)) return hipErrorInvalidValue;
+  if (ksa < 32 || ksa % 32 || ksb < 32 || ksb % 32) return hipErrorInvalidValue;
   const int tile = x3_tile_edge(M, N, sym);
   const int blocks = x3_blocks(M, N, sym);
   switch (pm) {
     case PM_X3:
-      x3_dispatch<PM_X3>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st);
+      x3_dispatch<PM_X3>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st, ksa,
+                          ksb);
       break;
     case PM_HH:
-      x3_dispatch<PM_HH>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st);
+      x3_dispatch<PM_HH>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st, ksa,
+                          ksb);
       break;
     case PM_X3F16:
-      x3_dispatch<PM_X3F16>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st);
+      x3_dispatch<PM_X3F16>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st, ksa,
+                          ksb);
       break;
     default:
-      x3_dispatch<PM_HHF16>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st);
+      x3_dispatch<PM_HHF16>(Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, sym, tile, blocks, ep, st, ksa,
+                          ksb);
   }
   return hipGetLastError();
 }

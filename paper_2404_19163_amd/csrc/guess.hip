@@ -315,7 +315,11 @@ __global__ void guess_write_kernel(const double* __restrict__ S, int n, const do
     if (z64r) z64r[e] = v;
     if (z64c) z64c[t] = v;
     if (zr_hi) { zr_hi[e] = h; zr_lo[e] = l; }
-    if (zc_hi) { zc_hi[t] = h; zc_lo[t] = l; }
+    if (zc_hi) {  // the transposed pair is K-blocked
+      const size_t kt = kb_offset(j, i, np);
+      zc_hi[kt] = h;
+      zc_lo[kt] = l;
+    }
   }
 }
 

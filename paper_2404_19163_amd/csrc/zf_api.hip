@@ -173,6 +173,8 @@ struct Workspace {
   std::vector<void*> allocs;
   // x3 operands (BF16 hi/lo pairs)
   u16 *s_hi = nullptr, *s_lo = nullptr;
+  // Z's pair row-major (zr) and transposed (zc); zc is K-blocked (kb_offset): the
+  // residual's products read it as their A operand, the update writes it by strips
   u16 *zr_hi[2] = {}, *zr_lo[2] = {}, *zc_hi[2] = {}, *zc_lo[2] = {};
   u16 *at_hi = nullptr, *at_lo = nullptr, *d_hi = nullptr, *d_lo = nullptr;
   u16 *q_hi = nullptr, *q_lo = nullptr, *u_hi = nullptr, *u_lo = nullptr;
@@ -362,8 +364,9 @@ static EpiParams epi0(int np, int n_valid) {
   return e;
 }
 
+// a_kb: A (np x np) is in the K-blocked layout (kb_offset), as Z's transposed pair is
 static int gemm_x3(const u16* Ah, const u16* Al, const u16* Bh, const u16* Bl, int np, bool sym,
-                   const EpiParams& ep, hipStream_t st, int pm = PM_X3) {
+                   const EpiParams& ep, hipStream_t st, int pm = PM_X3, bool a_kb = false) {
   PendingEvent pe{};
   const bool prof = g_prof.on;
   if (prof) {
@@ -377,7 +380,8 @@ static int gemm_x3(const u16* Ah, const u16* Al, const u16* Bh, const u16* Bl, i
     pe.flops = ((pm & PM_HH) ? 1.0 : 3.0) * 2.0 * (double)x3_blocks(np, np, sym) * t * t * (double)np;
     HIP_TRY(hipEventRecord(pe.a, st));
   }
-  HIP_TRY(launch_gemm_x3(Ah, Al, np, Bh, Bl, np, np, np, np, sym, ep, st, pm));
+  HIP_TRY(launch_gemm_x3(Ah, Al, a_kb ? 32 : np, Bh, Bl, np, np, np, np, sym, ep, st, pm,
+                         a_kb ? 32 * np : 32, 32));
   if (prof) {
     HIP_TRY(hipEventRecord(pe.b, st));
     g_prof.pending.push_back(pe);
@@ -541,14 +545,14 @@ static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
     e1.ohi = w.at_hi;
     e1.olo = w.at_lo;
     e1.pair_fmt = fmt;
-    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.s_hi, w.s_lo, np, false, e1, c.st, pm));
+    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.s_hi, w.s_lo, np, false, e1, c.st, pm, true));
     if (ar_f16(da)) {
       e2.o32 = e2.ot32 = w.dl32;
     } else {
       e2.ohi = e2.othi = w.d_hi;
       e2.olo = e2.otlo = w.d_lo;
     }
-    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.at_hi, w.at_lo, np, true, e2, c.st, pm));
+    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.at_hi, w.at_lo, np, true, e2, c.st, pm, true));
     blocks = x3_blocks(np, np, true);
   } else if (da == AR_EMU) {  // A^T = Z^T S and Z^T A, both emulated, A^T kept in FP64
     const int s = c.oz_slices;
@@ -687,6 +691,7 @@ static int update(Ctx& c, Arith da, Arith ca, bool high, int cur) {
     e.olo = w.zr_lo[nxt];
     e.othi = w.zc_hi[nxt];
     e.otlo = w.zc_lo[nxt];
+    e.t_kb = 1;  // Z's transposed pair is K-blocked
     return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], q.hi, q.lo, np, false, e, c.st, ar_pm(ca));
   }
   e.ot32 = w.zc32[nxt];
@@ -1181,8 +1186,9 @@ int zf_congruence(const double* H, const double* Z, int n, int precision, double
     e1.olo = w->at_lo;
     e1.pair_fmt = f16 ? PAIR_F16 : PAIR_BF16;
     e2.pair_fmt = e1.pair_fmt;
-    rc = gemm_x3(w->zc_hi[0], w->zc_lo[0], w->s_hi, w->s_lo, np, false, e1, st, ar_pm(ar));
-    if (!rc) rc = gemm_x3(w->zc_hi[0], w->zc_lo[0], w->at_hi, w->at_lo, np, true, e2, st, ar_pm(ar));
+    rc = gemm_x3(w->zc_hi[0], w->zc_lo[0], w->s_hi, w->s_lo, np, false, e1, st, ar_pm(ar), true);
+    if (!rc)
+      rc = gemm_x3(w->zc_hi[0], w->zc_lo[0], w->at_hi, w->at_lo, np, true, e2, st, ar_pm(ar), true);
   } else if (ar == AR_F32) {
     HIP_TRY(launch_split_pad(H, n, n, np, nullptr, nullptr, nullptr, w->s32, false, 1, st));
     HIP_TRY(launch_init_given(Z, n, np, w->z32[0], nullptr, nullptr, nullptr, nullptr, nullptr,

@@ -103,10 +103,23 @@ __host__ __device__ inline bool accept_poly(double c[3], double x_lo) {
 }
 
 // ---------------------------------------------------------------------------
+// K-blocked layout of a 16-bit operand with ld rows of stride 32: element (r, k)
+// of an (rows x K) operand at kb_offset(r, k, ld), i.e. K cut into blocks of 32
+// and each block stored as a row-major (ld x 32) panel.  One K step of a GEMM
+// tile then reads a contiguous run of 64-byte rows, and a producer that forms 32
+// consecutive k of many rows (a transposed epilogue strip) writes one contiguous
+// run instead of 64-byte pieces one ld apart.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline size_t kb_offset(int r, int k, int ld) {
+  return (size_t)(k >> 5) * ((size_t)ld << 5) + ((size_t)r << 5) + (size_t)(k & 31);
+}
+
+// ---------------------------------------------------------------------------
 // GEMM epilogue: out = alpha * D + beta * acc + gamma * I  (I restricted to the
 // valid n_valid x n_valid block so that zero padding stays exactly zero).
 // Every output pointer is optional.  Normal outputs are written at
-// [row * ld + col]; transposed outputs at [col * ld + row].  In symmetric mode
+// [row * ld + col]; transposed outputs at [col * ld + row], or, with t_kb (BF16x3
+// kernels, pair outputs only), at kb_offset(col, row, ld).  In symmetric mode
 // the caller passes the same matrices for both, and the kernel writes the upper
 // triangle normally and mirrors it.
 // ---------------------------------------------------------------------------
@@ -128,6 +141,7 @@ struct EpiParams {
   u16* otlo;
   double* partials;  // per-tile sum of out^2 (FP64), or nullptr
   int pair_fmt;      // PAIR_BF16 / PAIR_F16: format of dhi/dlo and of every pair output
+  int t_kb;          // othi/otlo in the K-blocked layout (no ot32/ot64 alongside)
 };
 
 // Launchers (return hipSuccess or the launch error).  All dimensions must be
@@ -139,10 +153,12 @@ int f64_tile_edge(int M, int N, bool sym);
 int f64_blocks(int M, int N, bool sym);
 int max_blocks(int M, int N);            // upper bound of the above (smallest tile edge)
 
-// pm: product mode PM_* (BF16 or FP16 halves; all three products or (h)(h) only)
+// pm: product mode PM_* (BF16 or FP16 halves; all three products or (h)(h) only).
+// Operand element (r, k) sits at r * ld + (k / 32) * ks + k % 32: ks = 32 for a
+// row-major operand, ld = 32 and ks = 32 * rows for a K-blocked one (kb_offset).
 hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bhi, const u16* Blo,
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
-                          hipStream_t st, int pm = PM_X3);
+                          hipStream_t st, int pm = PM_X3, int ksa = 32, int ksb = 32);
 int f32_tile_edge(int M, int N, bool sym);
 int f32_blocks(int M, int N, bool sym);
 hipError_t launch_gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int N, int K,
