@@ -17,7 +17,8 @@ static inline int grid_for(size_t work, int block) {
 
 // ---------------------------------------------------------------------------
 // S (n x n, ld_src) -> padded np x np: BF16 hi/lo pair (Sec. III.A: the FP64
-// value is first rounded to FP32, then split), optionally an FP64 / FP32 copy.
+// value is first rounded to FP32, then split) in the K-blocked layout of the
+// matrix-core operands (kb_offset), optionally an FP64 / FP32 row-major copy.
 // ---------------------------------------------------------------------------
 __global__ void split_pad_kernel(const double* __restrict__ src, int n, int ld_src, int np,
                                  u16* __restrict__ hi, u16* __restrict__ lo,
@@ -32,8 +33,9 @@ __global__ void split_pad_kernel(const double* __restrict__ src, int n, int ld_s
       u16 h, l;
       if (fmt == 2) split_f16(x, h, l);
       else split_bf16(x, h, l);
-      hi[e] = h;
-      lo[e] = l;
+      const size_t k = kb_offset(i, j, np);
+      hi[k] = h;
+      lo[k] = l;
     }
     if (c64) c64[e] = a;
     if (c32) c32[e] = x;
@@ -112,7 +114,8 @@ hipError_t launch_row_abs_max(const double* S, int n, int ld, double* row_sums, 
 
 // ---------------------------------------------------------------------------
 // Z0 = I / sqrt(g) in every layout the sweep reads (g read on the device).  The
-// transposed pair zc is K-blocked (kb_offset); the loop walks it in storage order.
+// pairs are K-blocked (kb_offset), where the row-major and the transposed pair of
+// the (symmetric) Z0 coincide; the loop walks them in storage order.
 // ---------------------------------------------------------------------------
 __global__ void init_identity_kernel(const double* __restrict__ g, int n, int np, float* z32,
                                      double* z64r, double* z64c, u16* zr_hi, u16* zr_lo,
@@ -124,20 +127,17 @@ __global__ void init_identity_kernel(const double* __restrict__ g, int n, int np
     const int i = (int)(e / np), j = (int)(e % np);
     const double v = (i == j && i < n) ? c : 0.0;
     const float f = (float)v;
-    u16 h, l;
-    split_bf16(f, h, l);
     if (z32) z32[e] = f;
     if (z64r) z64r[e] = v;
     if (z64c) z64c[e] = v;
-    if (zr_hi) { zr_hi[e] = h; zr_lo[e] = l; }
-    if (zc_hi) {  // storage element e of the K-blocked zc: k block e / (32 np), row, k % 32
+    if (zr_hi || zc_hi) {  // storage element e of a K-blocked pair: k block e / (32 np), row, k % 32
       const size_t panel = (size_t)np << 5;
       const int kk = (int)(e / panel) * 32 + (int)(e & 31), rr = (int)((e % panel) >> 5);
       const float fc = (rr == kk && rr < n) ? (float)c : 0.0f;
       u16 hc, lc;
       split_bf16(fc, hc, lc);
-      zc_hi[e] = hc;
-      zc_lo[e] = lc;
+      if (zr_hi) { zr_hi[e] = hc; zr_lo[e] = lc; }
+      if (zc_hi) { zc_hi[e] = hc; zc_lo[e] = lc; }
     }
   }
 }
@@ -152,9 +152,9 @@ hipError_t launch_init_identity(const double* g, int n, int np, float* z32, doub
 }
 
 // Given Z0 (n x n, ld n): padded copies in row-major and transposed layouts (the
-// transposed pair K-blocked, kb_offset).  One 64 x 64 tile per block; the transposed
-// copies go through a padded LDS tile so that Z0 is read, and every layout written,
-// in contiguous runs.  The pairs are the split of Z0's FP32 value.
+// pairs K-blocked, kb_offset).  One 64 x 64 tile per block; the transposed copies
+// go through a padded LDS tile so that Z0 is read, and every layout written, in
+// contiguous runs.  The pairs are the split of Z0's FP32 value.
 __global__ void __launch_bounds__(256) init_given_kernel(const double* __restrict__ Z0, int n,
                                                          int np, float* __restrict__ z32,
                                                          double* __restrict__ z64r,
@@ -175,8 +175,9 @@ __global__ void __launch_bounds__(256) init_given_kernel(const double* __restric
     if (zr_hi) {
       u16 h, l;
       split_bf16((float)v, h, l);
-      zr_hi[idx] = h;
-      zr_lo[idx] = l;
+      const size_t kidx = kb_offset(i, j, np);
+      zr_hi[kidx] = h;
+      zr_lo[kidx] = l;
     }
     t[r][c] = v;
   }
@@ -209,8 +210,8 @@ hipError_t launch_init_given(const double* Z0, int n, int np, float* z32, double
 
 // FP32 master -> FP64 row-major and transposed (start of the refinement phase).
 // FP32 matrix X (np x np, row-major) -> any of: FP64 row-major, FP64 transposed,
-// FP32 transposed, and 16-bit pairs (format fmt) of scale * X, row-major and/or
-// transposed (the transposed pair K-blocked, kb_offset, as Z's transposed pair is).
+// FP32 transposed, and 16-bit pairs (format fmt) of scale * X in the K-blocked
+// layout of the matrix-core operands (kb_offset), of X and/or of its transpose.
 // scale is a power of two (exact).  One 64 x 64 tile per block; the transposed
 // copies go through a padded LDS tile so that both layouts are read and written in
 // contiguous runs.
@@ -231,8 +232,9 @@ __global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ z3
     if (prh) {
       u16 h, l;
       split_pair(v * scale, h, l, fmt);
-      prh[idx] = h;
-      prl[idx] = l;
+      const size_t kidx = kb_offset(i0 + r, j0 + c, np);
+      prh[kidx] = h;
+      prl[kidx] = l;
     }
     t[r][c] = v;
   }

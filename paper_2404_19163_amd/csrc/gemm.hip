@@ -207,8 +207,6 @@ hipError_t launch_gemm_x3(const u16* Ahi, const u16* Alo, int lda, const u16* Bh
                           int ldb, int M, int N, int K, bool sym, const EpiParams& ep,
                           hipStream_t st, int pm, int ksa, int ksb) {
   if (!dims_ok(M, N, K, sym) || pm < 0 || pm > 3) return hipErrorInvalidValue;
-  // a K-blocked transposed output holds only 16-bit pairs; ks is 32 or a multiple of it
-  if (ep.t_kb && (ep.ot32 || ep.ot64)) return hipErrorInvalidValue;
   if (ksa < 32 || ksa % 32 || ksb < 32 || ksb % 32) return hipErrorInvalidValue;
   const int tile = x3_tile_edge(M, N, sym);
   const int blocks = x3_blocks(M, N, sym);

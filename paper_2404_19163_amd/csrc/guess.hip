@@ -314,8 +314,12 @@ __global__ void guess_write_kernel(const double* __restrict__ S, int n, const do
     if (z32) z32[e] = f;
     if (z64r) z64r[e] = v;
     if (z64c) z64c[t] = v;
-    if (zr_hi) { zr_hi[e] = h; zr_lo[e] = l; }
-    if (zc_hi) {  // the transposed pair is K-blocked
+    if (zr_hi) {  // both pairs are K-blocked
+      const size_t kr = kb_offset(i, j, np);
+      zr_hi[kr] = h;
+      zr_lo[kr] = l;
+    }
+    if (zc_hi) {
       const size_t kt = kb_offset(j, i, np);
       zc_hi[kt] = h;
       zc_lo[kt] = l;

@@ -173,8 +173,9 @@ struct Workspace {
   std::vector<void*> allocs;
   // x3 operands (BF16 hi/lo pairs)
   u16 *s_hi = nullptr, *s_lo = nullptr;
-  // Z's pair row-major (zr) and transposed (zc); zc is K-blocked (kb_offset): the
-  // residual's products read it as their A operand, the update writes it by strips
+  // Z's pair row-major (zr) and transposed (zc).  Every pair of the workspace is
+  // K-blocked (kb_offset): a K step of a GEMM tile reads one contiguous run, and
+  // the transposed epilogue writes one per strip.
   u16 *zr_hi[2] = {}, *zr_lo[2] = {}, *zc_hi[2] = {}, *zc_lo[2] = {};
   u16 *at_hi = nullptr, *at_lo = nullptr, *d_hi = nullptr, *d_lo = nullptr;
   u16 *q_hi = nullptr, *q_lo = nullptr, *u_hi = nullptr, *u_lo = nullptr;
@@ -361,12 +362,13 @@ static EpiParams epi0(int np, int n_valid) {
   e.gamma = 0.0;
   e.ld = np;
   e.n_valid = n_valid;
+  e.kb = 1;  // the workspace's 16-bit pairs are K-blocked
   return e;
 }
 
-// a_kb: A (np x np) is in the K-blocked layout (kb_offset), as Z's transposed pair is
+// Operands are workspace pairs (np x np), all in the K-blocked layout (kb_offset).
 static int gemm_x3(const u16* Ah, const u16* Al, const u16* Bh, const u16* Bl, int np, bool sym,
-                   const EpiParams& ep, hipStream_t st, int pm = PM_X3, bool a_kb = false) {
+                   const EpiParams& ep, hipStream_t st, int pm = PM_X3) {
   PendingEvent pe{};
   const bool prof = g_prof.on;
   if (prof) {
@@ -380,8 +382,7 @@ static int gemm_x3(const u16* Ah, const u16* Al, const u16* Bh, const u16* Bl, i
     pe.flops = ((pm & PM_HH) ? 1.0 : 3.0) * 2.0 * (double)x3_blocks(np, np, sym) * t * t * (double)np;
     HIP_TRY(hipEventRecord(pe.a, st));
   }
-  HIP_TRY(launch_gemm_x3(Ah, Al, a_kb ? 32 : np, Bh, Bl, np, np, np, np, sym, ep, st, pm,
-                         a_kb ? 32 * np : 32, 32));
+  HIP_TRY(launch_gemm_x3(Ah, Al, 32, Bh, Bl, 32, np, np, np, sym, ep, st, pm, 32 * np, 32 * np));
   if (prof) {
     HIP_TRY(hipEventRecord(pe.b, st));
     g_prof.pending.push_back(pe);
@@ -545,14 +546,14 @@ static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
     e1.ohi = w.at_hi;
     e1.olo = w.at_lo;
     e1.pair_fmt = fmt;
-    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.s_hi, w.s_lo, np, false, e1, c.st, pm, true));
+    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.s_hi, w.s_lo, np, false, e1, c.st, pm));
     if (ar_f16(da)) {
       e2.o32 = e2.ot32 = w.dl32;
     } else {
       e2.ohi = e2.othi = w.d_hi;
       e2.olo = e2.otlo = w.d_lo;
     }
-    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.at_hi, w.at_lo, np, true, e2, c.st, pm, true));
+    ZF_TRY(gemm_x3(w.zc_hi[cur], w.zc_lo[cur], w.at_hi, w.at_lo, np, true, e2, c.st, pm));
     blocks = x3_blocks(np, np, true);
   } else if (da == AR_EMU) {  // A^T = Z^T S and Z^T A, both emulated, A^T kept in FP64
     const int s = c.oz_slices;
@@ -691,7 +692,6 @@ static int update(Ctx& c, Arith da, Arith ca, bool high, int cur) {
     e.olo = w.zr_lo[nxt];
     e.othi = w.zc_hi[nxt];
     e.otlo = w.zc_lo[nxt];
-    e.t_kb = 1;  // Z's transposed pair is K-blocked
     return gemm_x3(w.zr_hi[cur], w.zr_lo[cur], q.hi, q.lo, np, false, e, c.st, ar_pm(ca));
   }
   e.ot32 = w.zc32[nxt];
@@ -1186,9 +1186,8 @@ int zf_congruence(const double* H, const double* Z, int n, int precision, double
     e1.olo = w->at_lo;
     e1.pair_fmt = f16 ? PAIR_F16 : PAIR_BF16;
     e2.pair_fmt = e1.pair_fmt;
-    rc = gemm_x3(w->zc_hi[0], w->zc_lo[0], w->s_hi, w->s_lo, np, false, e1, st, ar_pm(ar), true);
-    if (!rc)
-      rc = gemm_x3(w->zc_hi[0], w->zc_lo[0], w->at_hi, w->at_lo, np, true, e2, st, ar_pm(ar), true);
+    rc = gemm_x3(w->zc_hi[0], w->zc_lo[0], w->s_hi, w->s_lo, np, false, e1, st, ar_pm(ar));
+    if (!rc) rc = gemm_x3(w->zc_hi[0], w->zc_lo[0], w->at_hi, w->at_lo, np, true, e2, st, ar_pm(ar));
   } else if (ar == AR_F32) {
     HIP_TRY(launch_split_pad(H, n, n, np, nullptr, nullptr, nullptr, w->s32, false, 1, st));
     HIP_TRY(launch_init_given(Z, n, np, w->z32[0], nullptr, nullptr, nullptr, nullptr, nullptr,
@@ -1372,6 +1371,7 @@ static int t_gemm_impl(int precision, int oz_slices, int sym, int m, int nn, int
   if (D) pad_in(D, m, nn, d64);
   if (he == hipSuccess) he = hipMemsetAsync(c64, 0, e * 8, st);
   EpiParams ep = epi0(np, m < nn ? m : nn);
+  ep.kb = 0;  // this entry's operands and outputs are row-major
   ep.alpha = alpha;
   ep.beta = beta;
   ep.gamma = gamma;

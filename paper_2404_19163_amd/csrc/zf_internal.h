@@ -118,10 +118,12 @@ __host__ __device__ inline size_t kb_offset(int r, int k, int ld) {
 // GEMM epilogue: out = alpha * D + beta * acc + gamma * I  (I restricted to the
 // valid n_valid x n_valid block so that zero padding stays exactly zero).
 // Every output pointer is optional.  Normal outputs are written at
-// [row * ld + col]; transposed outputs at [col * ld + row], or, with t_kb (BF16x3
-// kernels, pair outputs only), at kb_offset(col, row, ld).  In symmetric mode
-// the caller passes the same matrices for both, and the kernel writes the upper
-// triangle normally and mirrors it.
+// [row * ld + col]; transposed outputs at [col * ld + row].  With kb set, every
+// 16-bit pair read or written (dhi/dlo, ohi/olo, othi/otlo) is K-blocked instead:
+// (row, col) at kb_offset(row, col, ld), the transposed one at kb_offset(col, row,
+// ld); FP32 and FP64 matrices stay row-major.  In symmetric mode the caller passes
+// the same matrices for both, and the kernel writes the upper triangle normally
+// and mirrors it.
 // ---------------------------------------------------------------------------
 struct EpiParams {
   double alpha, beta, gamma;
@@ -141,7 +143,7 @@ struct EpiParams {
   u16* otlo;
   double* partials;  // per-tile sum of out^2 (FP64), or nullptr
   int pair_fmt;      // PAIR_BF16 / PAIR_F16: format of dhi/dlo and of every pair output
-  int t_kb;          // othi/otlo in the K-blocked layout (no ot32/ot64 alongside)
+  int kb;            // 16-bit pairs in the K-blocked layout (kb_offset)
 };
 
 // Launchers (return hipSuccess or the launch error).  All dimensions must be
