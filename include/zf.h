@@ -348,6 +348,19 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
               double* norm_sq, void* stream);
 
 /*
+ * zf_t_gemm_kb -- zf_t_gemm for the 16-bit-pair precisions (ZF_BF16X3, ZF_BF16,
+ * ZF_FP16X3, ZF_FP16) with both operands split into the K-blocked layout that the
+ * solver keeps its pairs in: with r rows (padded), element (i, k) at
+ * (k / 32) * 32 r + 32 i + k % 32, i.e. 32-wide blocks of the contracted index, each
+ * a row-major panel.  The products and their summation order are those of
+ * zf_t_gemm, so C and norm_sq equal its results bit for bit.  Other precisions
+ * return ZF_ERR_ARG.
+ */
+int zf_t_gemm_kb(int precision, int sym, int m, int nn, int k, const double* A, const double* B,
+                 double alpha, const double* D, double beta, double gamma, double* C,
+                 double* norm_sq, void* stream);
+
+/*
  * zf_t_ozaki -- zf_t_gemm's product and epilogue with A B^T emulated from `slices`
  * (1..8) 7-bit integer slices per operand row on the int8 matrix cores (the
  * refinement residual's arithmetic under ZF_REFINE_EMU): row i of A is scaled by

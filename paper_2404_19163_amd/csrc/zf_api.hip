@@ -1319,7 +1319,8 @@ int zf_t_split(const double* a, int64_t count, uint16_t* hi, uint16_t* lo, int f
 // the residue-emulated product with oz_slices moduli (zf_t_crt)
 static int t_gemm_impl(int precision, int oz_slices, int sym, int m, int nn, int k,
                        const double* A, const double* B, double alpha, const double* D,
-                       double beta, double gamma, double* C, double* norm_sq, void* stream) {
+                       double beta, double gamma, double* C, double* norm_sq, void* stream,
+                       bool kb = false) {
   if (!A || !B || !C || m <= 0 || nn <= 0 || k <= 0) return fail(ZF_ERR_ARG, "bad gemm arguments");
   if (sym && m != nn) return fail(ZF_ERR_ARG, "symmetric mode needs m == nn");
   const bool crt = precision == -2;
@@ -1428,10 +1429,19 @@ static int t_gemm_impl(int precision, int oz_slices, int sym, int m, int nn, int
       cleanup();
       return rc;
     }
-    he = launch_split_flat(a64, (int64_t)e, ah, al, f16 ? 2 : 1, st);
-    if (he == hipSuccess) he = launch_split_flat(b64, (int64_t)e, bh, bl, f16 ? 2 : 1, st);
-    if (he == hipSuccess)
-      he = launch_gemm_x3(ah, al, np, bh, bl, np, np, np, np, sym != 0, ep, st, pm);
+    if (kb) {  // the solver's K-blocked pairs (split_pad writes that layout)
+      he = launch_split_pad(a64, np, np, np, ah, al, nullptr, nullptr, false, f16 ? 2 : 1, st);
+      if (he == hipSuccess)
+        he = launch_split_pad(b64, np, np, np, bh, bl, nullptr, nullptr, false, f16 ? 2 : 1, st);
+      if (he == hipSuccess)
+        he = launch_gemm_x3(ah, al, 32, bh, bl, 32, np, np, np, sym != 0, ep, st, pm, 32 * np,
+                            32 * np);
+    } else {
+      he = launch_split_flat(a64, (int64_t)e, ah, al, f16 ? 2 : 1, st);
+      if (he == hipSuccess) he = launch_split_flat(b64, (int64_t)e, bh, bl, f16 ? 2 : 1, st);
+      if (he == hipSuccess)
+        he = launch_gemm_x3(ah, al, np, bh, bl, np, np, np, np, sym != 0, ep, st, pm);
+    }
   } else if (he == hipSuccess) {
     he = launch_gemm_f64(a64, np, b64, np, np, np, np, sym != 0, ep, st);
   }
@@ -1465,6 +1475,16 @@ int zf_t_gemm(int precision, int sym, int m, int nn, int k, const double* A, con
               void* stream) {
   if (precision < ZF_FP64) return fail(ZF_ERR_ARG, "precision %d not supported", precision);
   return t_gemm_impl(precision, 0, sym, m, nn, k, A, B, alpha, D, beta, gamma, C, norm_sq, stream);
+}
+
+int zf_t_gemm_kb(int precision, int sym, int m, int nn, int k, const double* A, const double* B,
+                 double alpha, const double* D, double beta, double gamma, double* C,
+                 double* norm_sq, void* stream) {
+  if (precision != ZF_BF16X3 && precision != ZF_BF16 && precision != ZF_FP16X3 &&
+      precision != ZF_FP16)
+    return fail(ZF_ERR_ARG, "precision %d has no 16-bit pairs", precision);
+  return t_gemm_impl(precision, 0, sym, m, nn, k, A, B, alpha, D, beta, gamma, C, norm_sq, stream,
+                     true);
 }
 
 int zf_t_crt(int moduli, int sym, int m, int nn, int k, const double* A, const double* B,

@@ -65,7 +65,7 @@ EXPORTS = ("zf_default_opts", "zf_refine", "zf_refine_ex", "zf_residual", "zf_re
            "zf_batched_release", "zf_features", "zf_guess_label",
            "zf_mlp_set_params", "zf_mlp_get_params", "zf_mlp_set_norm", "zf_mlp_train_step",
            "zf_mlp_grad", "zf_mlp_predict", "zf_mlp_save", "zf_mlp_load", "zf_congruence", "zf_t_ozaki",
-           "zf_t_crt")
+           "zf_t_crt", "zf_t_gemm_kb")
 N_PARAMS = 4931
 
 _lib = None
@@ -103,6 +103,8 @@ def lib() -> ctypes.CDLL:
     L.zf_t_split.restype = i
     L.zf_t_gemm.argtypes = [i, i, i, i, i, vp, vp, d, vp, d, d, vp, P(d), vp]
     L.zf_t_gemm.restype = i
+    L.zf_t_gemm_kb.argtypes = [i, i, i, i, i, vp, vp, d, vp, d, d, vp, P(d), vp]
+    L.zf_t_gemm_kb.restype = i
     L.zf_t_ozaki.argtypes = [i, i, i, i, i, vp, vp, d, vp, d, d, vp, P(d), vp]
     L.zf_t_ozaki.restype = i
     L.zf_t_crt.argtypes = [i, i, i, i, i, vp, vp, d, vp, d, d, vp, P(d), vp]
@@ -375,10 +377,11 @@ def t_split(a: torch.Tensor, fmt: str = "bf16", stream=None):
 
 def t_gemm(precision: str, A: torch.Tensor, B: torch.Tensor, *, sym: bool = False,
            alpha: float = 0.0, D: torch.Tensor | None = None, beta: float = 1.0,
-           gamma: float = 0.0, stream=None, slices: int = 0):
+           gamma: float = 0.0, stream=None, slices: int = 0, kblocked: bool = False):
     """C = alpha D + beta A B^T + gamma I through one library GEMM; returns (C, sum C^2).
     precision "emu" runs the emulated FP64 product with `slices` integer slices, "crt"
-    the residue-emulated product with `slices` moduli."""
+    the residue-emulated product with `slices` moduli; kblocked (pair precisions) splits
+    A and B into the solver's K-blocked pair layout (zf_t_gemm_kb)."""
     m, k = A.shape
     nn = B.shape[0]
     for t, nm in ((A, "A"), (B, "B")):
@@ -397,7 +400,8 @@ def t_gemm(precision: str, A: torch.Tensor, B: torch.Tensor, *, sym: bool = Fals
         rc = fn(slices, 1 if sym else 0, m, nn, k, A.data_ptr(), B.data_ptr(), alpha,
                 dptr, beta, gamma, C.data_ptr(), ctypes.byref(nrm), _stream(stream))
     else:
-        rc = lib().zf_t_gemm(_PREC[precision], 1 if sym else 0, m, nn, k, A.data_ptr(),
+        fn = lib().zf_t_gemm_kb if kblocked else lib().zf_t_gemm
+        rc = fn(_PREC[precision], 1 if sym else 0, m, nn, k, A.data_ptr(),
                              B.data_ptr(), alpha, dptr, beta, gamma, C.data_ptr(),
                              ctypes.byref(nrm), _stream(stream))
     _check(rc)

@@ -311,3 +311,26 @@ def test_gemm_symmetric_delta_n4096(zf, k):
     up = np.triu(np.ones((n, n), dtype=bool))
     assert np.all((np.abs(C - ref) <= tol)[up])
     assert nsq == pytest.approx(math.fsum((C * C).ravel().tolist()), rel=1e-12)
+
+
+@pytest.mark.parametrize("tile", ["64", "128", "256"])
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16", "fp16x3"])
+@pytest.mark.parametrize("sym", [False, True])
+def test_gemm_kblocked_operands_bitwise(zf, prec, sym, tile, monkeypatch):
+    """The solver keeps its pairs K-blocked (32-wide K panels): the same products in the
+    same order as the row-major operands, so C and the norm agree bit for bit, on every
+    tile edge and on a ragged size (padded to 768, three 256-wide K blocks of panels)."""
+    monkeypatch.setenv("ZF_X3_TILE", tile)
+    monkeypatch.setenv("ZF_X3_SYM_TILE", tile)
+    rng = np.random.default_rng(17 + len(prec) + 2 * int(tile) + sym)
+    n, k = 700, 700
+    A = rng.standard_normal((n, k))
+    B = A @ np.diag(rng.uniform(0.5, 2.0, k)) if sym else rng.standard_normal((n, k))
+    D = rng.standard_normal((n, n))
+    if sym:
+        D = D + D.T
+    args = dict(sym=sym, alpha=0.5, D=_cuda(D), beta=-1.0, gamma=1.0)
+    C_rm, n_rm = zf.t_gemm(prec, _cuda(A), _cuda(B), **args)
+    C_kb, n_kb = zf.t_gemm(prec, _cuda(A), _cuda(B), kblocked=True, **args)
+    assert torch.equal(C_rm, C_kb)
+    assert n_rm == n_kb
