@@ -140,6 +140,7 @@ __global__ void __launch_bounds__(X3G<T>::NT, 2)
     ep.beta = 1.0;
     ep.ld = np;
     ep.n_valid = M.n;
+    ep.kb = 1;  // the arena's pairs are K-blocked (kb_offset)
     const u16 *ah, *al, *bh, *bl;
     int mode = 0, pidx = 0;
     if (op == OP_L1) {
@@ -201,8 +202,8 @@ __global__ void __launch_bounds__(X3G<T>::NT, 2)
       const int tiles = np / T;
       pidx = tk.ti * tiles - tk.ti * (tk.ti - 1) / 2 + (tk.tj - tk.ti);
     }
-    x3_tile<T, T, 32, 2, 2>(ah, al, np, bh, bl, np, np, tk.ti * T, tk.tj * T, mode, ep, pidx, lds,
-                            red);
+    x3_tile<T, T, 32, 2, 2>(ah, al, 32, bh, bl, 32, np, tk.ti * T, tk.tj * T, mode, ep, pidx, lds,
+                            red, 32 * np, 32 * np);
     __syncthreads();
   }
 }
@@ -229,6 +230,7 @@ __global__ void __launch_bounds__(256, 4)
     ep.beta = 1.0;
     ep.ld = np;
     ep.n_valid = M.n;
+    ep.kb = 1;  // the delta pair it writes is K-blocked
     const double *a, *b;
     int mode = 0, pidx = 0;
     if (op == OP_H1) {
@@ -392,7 +394,8 @@ __device__ __forceinline__ bool tile_of(const BMat& M, int& i0, int& j0) {
   return true;
 }
 
-// S_m (n x n) -> BF16 pair and (optionally) FP64 copy, zero-padded to np x np
+// S_m (n x n) -> BF16 pair (K-blocked, kb_offset) and (optionally) FP64 copy,
+// zero-padded to np x np
 __global__ void __launch_bounds__(256) b_split_kernel(const BMat* __restrict__ mats,
                                                       const double* const* S, int with64) {
   const BMat& M = mats[blockIdx.y];
@@ -405,8 +408,9 @@ __global__ void __launch_bounds__(256) b_split_kernel(const BMat* __restrict__ m
     const size_t le = (size_t)i * M.np + j;
     u16 h, l;
     split_bf16((float)a, h, l);
-    M.s_hi[le] = h;
-    M.s_lo[le] = l;
+    const size_t ke = kb_offset(i, j, M.np);
+    M.s_hi[ke] = h;
+    M.s_lo[ke] = l;
     if (with64) M.s64[le] = a;
   }
 }
@@ -533,8 +537,8 @@ __global__ void b_accept_kernel(BMat* mats, int count, const double* __restrict_
   }
 }
 
-// Z0 into Z32, Zr and Zc of buffer 0: given, learned (c0 I + c1 S/g + c2 (S/g)^2) /
-// sqrt(g) with S^2 from z32[1], or I / sqrt(g)
+// Z0 into Z32, Zr and Zc of buffer 0 (the pairs K-blocked): given, learned (c0 I +
+// c1 S/g + c2 (S/g)^2) / sqrt(g) with S^2 from z32[1], or I / sqrt(g)
 __global__ void __launch_bounds__(256) b_init_kernel(const BMat* __restrict__ mats,
                                                      const double* const* Z0, const double* const* S,
                                                      const double* __restrict__ g,
@@ -572,15 +576,16 @@ __global__ void __launch_bounds__(256) b_init_kernel(const BMat* __restrict__ ma
     u16 h, l;
     split_bf16(f, h, l);
     M.z32[0][le] = f;
-    M.zr_hi[0][le] = h;
-    M.zr_lo[0][le] = l;
+    const size_t ke = kb_offset(i, j, np);
+    M.zr_hi[0][ke] = h;
+    M.zr_lo[0][ke] = l;
     th[r][c] = h;
     tl[r][c] = l;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < kET * kET; e += 256) {
     const int r = e / kET, c = e % kET;  // transposed row j0 + r, column i0 + c
-    const size_t t = (size_t)(j0 + r) * np + i0 + c;
+    const size_t t = kb_offset(j0 + r, i0 + c, np);
     M.zc_hi[0][t] = th[c][r];
     M.zc_lo[0][t] = tl[c][r];
   }
