@@ -53,21 +53,46 @@ struct CrtConsts {
 // One block per row: the row's largest magnitude and exponent, then for 4
 // consecutive columns per thread the integer a = trunc(x 2^(beta - e)) (|a| < 2^52,
 // exact) and its balanced residue modulo each m_l (one 4-byte store per plane).
-template <int L>
+template <int L, int R>
 __global__ void __launch_bounds__(256) crt_residue_kernel(const double* __restrict__ Mat, int np,
                                                           size_t plane, int beta,
                                                           signed char* __restrict__ out,
                                                           int* __restrict__ ex) {
+  // R > 0: the row (np <= 1024 R) is read once, into registers, 4 consecutive values
+  // per thread and 1024-element chunk; R = 0: read twice (maximum, then residues).
   __shared__ double red[4];
   __shared__ int bad_s[4];
   const int row = blockIdx.x;
   const double* r = Mat + (size_t)row * np;
   double m = 0.0;
   int bad = 0;
-  for (int k = threadIdx.x; k < np; k += 256) {
-    const double v = r[k];
-    bad |= !isfinite(v);
-    m = fmax(m, fabs(v));
+  double v[R > 0 ? R : 1][4];
+  if constexpr (R > 0) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const int k0 = threadIdx.x * 4 + 1024 * c;
+      if (k0 < np) {  // np is a multiple of 256, so all 4 are inside
+        const double2 u = *reinterpret_cast<const double2*>(r + k0);
+        const double2 w = *reinterpret_cast<const double2*>(r + k0 + 2);
+        v[c][0] = u.x;
+        v[c][1] = u.y;
+        v[c][2] = w.x;
+        v[c][3] = w.y;
+      } else {
+        v[c][0] = v[c][1] = v[c][2] = v[c][3] = 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        bad |= !isfinite(v[c][q]);
+        m = fmax(m, fabs(v[c][q]));
+      }
+    }
+  } else {
+    for (int k = threadIdx.x; k < np; k += 256) {
+      const double x = r[k];
+      bad |= !isfinite(x);
+      m = fmax(m, fabs(x));
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -84,10 +109,11 @@ __global__ void __launch_bounds__(256) crt_residue_kernel(const double* __restri
   int e = 0;
   if (m > 0.0 && !bad) (void)frexp(m, &e);
   if (threadIdx.x == 0) ex[row] = bad ? kCrtBad : e;
-  for (int k0 = threadIdx.x * 4; k0 < np; k0 += 1024) {
+  // residues of the 4 values x at k0 .., one packed 4-byte word per modulus
+  auto residues = [&](int k0, const double x[4]) __attribute__((always_inline)) {
     double a[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = bad ? 0.0 : trunc(ldexp(r[k0 + q], beta - e));
+    for (int q = 0; q < 4; ++q) a[q] = bad ? 0.0 : trunc(ldexp(x[q], beta - e));
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       const int md = crt_mod(l);
@@ -103,6 +129,18 @@ __global__ void __launch_bounds__(256) crt_residue_kernel(const double* __restri
         packed |= ((unsigned)ri & 0xffu) << (8 * q);
       }
       *reinterpret_cast<unsigned*>(out + l * plane + (size_t)row * np + k0) = packed;
+    }
+  };
+  if constexpr (R > 0) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const int k0 = threadIdx.x * 4 + 1024 * c;
+      if (k0 < np) residues(k0, v[c]);
+    }
+  } else {
+    for (int k0 = threadIdx.x * 4; k0 < np; k0 += 1024) {
+      const double x[4] = {r[k0], r[k0 + 1], r[k0 + 2], r[k0 + 3]};
+      residues(k0, x);
     }
   }
 }
@@ -297,10 +335,15 @@ hipError_t launch_crt_residues(const double* Mat, int np, int L, long long K, si
   CrtConsts cc;
   if (np <= 0 || np % 256 != 0 || !crt_consts(L, K, cc)) return hipErrorInvalidValue;
   const size_t plane = (size_t)np * np;
+  // rows of up to 8192 values stay in registers between the maximum and the residues
 #define ZF_CRT_RES(LL)                                                                        \
   case LL:                                                                                     \
-    hipLaunchKernelGGL(crt_residue_kernel<LL>, dim3(np), dim3(256), 0, st, Mat, np, plane,     \
-                       cc.beta, out, ex);                                                      \
+    if (np <= 8192)                                                                            \
+      hipLaunchKernelGGL((crt_residue_kernel<LL, 8>), dim3(np), dim3(256), 0, st, Mat, np,     \
+                         plane, cc.beta, out, ex);                                             \
+    else                                                                                       \
+      hipLaunchKernelGGL((crt_residue_kernel<LL, 0>), dim3(np), dim3(256), 0, st, Mat, np,     \
+                         plane, cc.beta, out, ex);                                             \
     break;
   switch (L) {
     ZF_CRT_RES(2) ZF_CRT_RES(3) ZF_CRT_RES(4) ZF_CRT_RES(5) ZF_CRT_RES(6) ZF_CRT_RES(7)
