@@ -57,7 +57,9 @@ template <int L, int R>
 __global__ void __launch_bounds__(256) crt_residue_kernel(const double* __restrict__ Mat, int np,
                                                           size_t plane, int beta,
                                                           signed char* __restrict__ out,
-                                                          int* __restrict__ ex) {
+                                                          int* __restrict__ ex,
+                                                          const int* __restrict__ gate) {
+  if (gate && *gate) return;
   // R > 0: the row (np <= 1024 R) is read once, into registers, 4 consecutive values
   // per thread and 1024-element chunk; R = 0: read twice (maximum, then residues).
   __shared__ double red[4];
@@ -160,7 +162,9 @@ template <bool SYM>
 __global__ void __launch_bounds__(512)
     crt_gemm_kernel(const u16* __restrict__ A, const u16* __restrict__ B, int ld16,
                     size_t plane16, int K16, int tiles_n, int gm, CrtConsts cc,
-                    unsigned char* __restrict__ rho, size_t plane, int np) {
+                    unsigned char* __restrict__ rho, size_t plane, int np,
+                    const int* __restrict__ gate) {
+  if (gate && *gate) return;
   constexpr int BM = 256, BN = 256, WM = 2, WN = 4, NS = 3;
   using C = X3Cfg<BM, BN, 32, WM, WN>;
   // single-product stages of (BM + BN) 32 elements: a 3-stage ring, two stages loading
@@ -244,6 +248,7 @@ __global__ void __launch_bounds__(256)
                            const int* __restrict__ ea, const int* __restrict__ eb, int sym,
                            CrtConsts cc, EpiParams ep) {
   __shared__ double red[4];
+  if (ep.gate && *ep.gate) return;
   const int T = np / 64;
   int ti, tj;
   tile_coords(blockIdx.x, T, sym != 0, ti, tj, 1);
@@ -331,7 +336,7 @@ int crt_beta(int L, long long K) {
 }
 
 hipError_t launch_crt_residues(const double* Mat, int np, int L, long long K, signed char* out,
-                               int* ex, hipStream_t st) {
+                               int* ex, hipStream_t st, const int* gate) {
   CrtConsts cc;
   if (np <= 0 || np % 256 != 0 || !crt_consts(L, K, cc)) return hipErrorInvalidValue;
   const size_t plane = (size_t)np * np;
@@ -340,10 +345,10 @@ hipError_t launch_crt_residues(const double* Mat, int np, int L, long long K, si
   case LL:                                                                                     \
     if (np <= 8192)                                                                            \
       hipLaunchKernelGGL((crt_residue_kernel<LL, 8>), dim3(np), dim3(256), 0, st, Mat, np,     \
-                         plane, cc.beta, out, ex);                                             \
+                         plane, cc.beta, out, ex, gate);                                       \
     else                                                                                       \
       hipLaunchKernelGGL((crt_residue_kernel<LL, 0>), dim3(np), dim3(256), 0, st, Mat, np,     \
-                         plane, cc.beta, out, ex);                                             \
+                         plane, cc.beta, out, ex, gate);                                       \
     break;
   switch (L) {
     ZF_CRT_RES(2) ZF_CRT_RES(3) ZF_CRT_RES(4) ZF_CRT_RES(5) ZF_CRT_RES(6) ZF_CRT_RES(7)
@@ -374,10 +379,11 @@ hipError_t launch_crt_product(const signed char* A, const int* ea, const signed 
   const size_t plane16 = (size_t)np * np / 2, plane = (size_t)np * np;
   if (sym)
     hipLaunchKernelGGL(crt_gemm_kernel<true>, dim3(blocks), dim3(512), 0, st, a16, b16, np / 2,
-                       plane16, np / 2, tiles, 1, cc, rho, plane, np);
+                       plane16, np / 2, tiles, 1, cc, rho, plane, np, ep.gate);
   else
     hipLaunchKernelGGL(crt_gemm_kernel<false>, dim3(blocks), dim3(512), 0, st, a16, b16, np / 2,
-                       plane16, np / 2, tiles, tiles % 4 == 0 ? 4 : 1, cc, rho, plane, np);
+                       plane16, np / 2, tiles, tiles % 4 == 0 ? 4 : 1, cc, rho, plane, np,
+                       ep.gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 grid(crt_blocks(np, sym));

@@ -318,6 +318,42 @@ hipError_t launch_norm_finalize(const double* partials, int count, double* out, 
   return hipGetLastError();
 }
 
+// Err of the sweep (the same fixed-order sum as norm_finalize_kernel), then the stop
+// test of Algorithm 2 (Sec. IV.A) on the device; see launch_norm_decide.
+__global__ void norm_decide_kernel(const double* __restrict__ partials, int count, int it,
+                                   int rule, int pw, int* gate, double* state, double* box) {
+  __shared__ double red[256];
+  if (*gate) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) s += partials[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double err = sqrt(red[0]);
+  int code = 0;
+  if (!isfinite(err)) {
+    code = 2;
+  } else if (it > 0) {
+    const double prev = state[0];
+    code = rule == 1 ? (err >= prev) : (err > pow(prev, (double)pw));
+  }
+  if (code) *gate = 1;
+  else state[0] = err;
+  box[0] = err;
+  box[1] = (double)code;
+}
+
+hipError_t launch_norm_decide(const double* partials, int count, int it, int rule, int pw,
+                              int* gate, double* state, double* box, hipStream_t st) {
+  hipLaunchKernelGGL(norm_decide_kernel, dim3(1), dim3(256), 0, st, partials, count, it, rule, pw,
+                     gate, state, box);
+  return hipGetLastError();
+}
+
 __global__ void fill_zero_kernel(uint32_t* p, size_t words) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < words;
        e += (size_t)gridDim.x * blockDim.x)

@@ -39,6 +39,7 @@ __global__ void __launch_bounds__(WM* WN * 64)
   using C = X3Cfg<BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) u16 lds[NS * C::STAGE_ELEMS];
   __shared__ double red[C::NT / 64];
+  if (ep.gate && *ep.gate) return;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   int ti, tj;
   tile_coords(bid, tiles_n, SYM, ti, tj, gm);
@@ -55,6 +56,7 @@ __global__ void __launch_bounds__(WM* WN * 64)
   using C = X3Cfg<BM, BN, 32, WM, WN>;
   __shared__ __attribute__((aligned(16))) u16 lds[2 * C::STAGE_ELEMS];
   __shared__ double red[C::NT / 64];
+  if (ep.gate && *ep.gate) return;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   int ti, tj;
   tile_coords(bid, tiles_n, SYM, ti, tj, gm);
@@ -79,6 +81,7 @@ __global__ void __launch_bounds__(WM* WN * 64, 2)
   using C = F64Cfg<BM, BN, BK, WM, WN>;
   __shared__ double lds[2 * C::STAGE];
   __shared__ double red[C::NT / 64];
+  if (ep.gate && *ep.gate) return;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   int ti, tj;
   tile_coords(bid, tiles_n, SYM, ti, tj, gm);

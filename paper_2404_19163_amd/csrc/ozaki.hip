@@ -36,8 +36,10 @@ constexpr int kOzBad = INT_MIN;
 __global__ void __launch_bounds__(256) oz_slice_kernel(const double* __restrict__ M, int np,
                                                        int s, size_t plane,
                                                        signed char* __restrict__ out,
-                                                       int* __restrict__ ex) {
+                                                       int* __restrict__ ex,
+                                                       const int* __restrict__ gate) {
   __shared__ double red[4];
+  if (gate && *gate) return;
   __shared__ int bad_s[4];
   const int row = blockIdx.x;
   const double* r = M + (size_t)row * np;
@@ -82,10 +84,10 @@ __global__ void __launch_bounds__(256) oz_slice_kernel(const double* __restrict_
 }
 
 hipError_t launch_oz_slice(const double* M, int np, int s, signed char* out, int* ex,
-                           hipStream_t st) {
+                           hipStream_t st, const int* gate) {
   if (np <= 0 || np % 128 != 0 || s < 1 || s > kOzMaxSlices) return hipErrorInvalidValue;
   hipLaunchKernelGGL(oz_slice_kernel, dim3(np), dim3(256), 0, st, M, np, s, (size_t)np * np, out,
-                     ex);
+                     ex, gate);
   return hipGetLastError();
 }
 
@@ -98,6 +100,7 @@ __global__ void __launch_bounds__(WM* WN * 64, 2)
   using C = X3Cfg<BM, BN, 32, WM, WN>;
   __shared__ __attribute__((aligned(16))) u16 lds[2 * C::STAGE_ELEMS];
   __shared__ double red[C::NT / 64];
+  if (ep.gate && *ep.gate) return;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   int ti, tj;
   tile_coords(bid, tiles_n, SYM, ti, tj, gm);

@@ -125,6 +125,7 @@ struct PendingEvent {
   hipEvent_t a, b;
   int cls;
   double flops;
+  bool skip;  // a launch the stop test's gate turned into a no-op: not counted
 };
 
 struct Profiler {
@@ -152,7 +153,7 @@ static hipEvent_t take_event() {
 static void prof_harvest() {
   for (auto& p : g_prof.pending) {
     float t = 0.f;
-    if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+    if (!p.skip && hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
       g_prof.launches[p.cls] += 1;
       g_prof.ms[p.cls] += t;
       g_prof.flops[p.cls] += p.flops;
@@ -201,7 +202,14 @@ struct Workspace {
   double *gscr = nullptr, *cg = nullptr;  // learned-guess scratch (8192) and coefficients (8)
   float* feats = nullptr;
   double* host_err = nullptr;  // pinned
+  // device-side stop test: the phase's gate (nonzero once it stopped), the previous
+  // Err, and a ring of kBoxSlots {Err, decision} pairs the host reads (pinned, coherent,
+  // written by the device; box_dev is its device address)
+  int* gate = nullptr;
+  double* prev_dev = nullptr;
+  double *box = nullptr, *box_dev = nullptr;
 };
+constexpr int kBoxSlots = 8;
 
 static Workspace g_ws;
 
@@ -209,6 +217,7 @@ static void ws_free(Workspace& w) {
   for (void* p : w.allocs) hipFree(p);
   w.allocs.clear();
   if (w.host_err) hipHostFree(w.host_err);
+  if (w.box) hipHostFree(w.box);
   int dev = w.device;
   w = Workspace();
   w.device = dev;
@@ -255,6 +264,14 @@ static int ws_build(Workspace& w, int dev, int np, bool x3, bool f64, bool f32, 
     (void)hipGetLastError();
     w.host_err = nullptr;
     return fail(ZF_ERR_NOMEM, "hipHostMalloc of the pinned norm word failed");
+  }
+  ZF_TRY(ws_alloc(w, &w.gate, 2));
+  ZF_TRY(ws_alloc(w, &w.prev_dev, 1));
+  if (hipHostMalloc((void**)&w.box, 2 * kBoxSlots * sizeof(double),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&w.box_dev, w.box, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ZF_ERR_NOMEM, "hipHostMalloc of the stop-test mailbox failed");
   }
   // the BF16 pairs of delta and Q and the row-major Z pair serve both phases
   ZF_TRY(ws_alloc(w, &w.d_hi, m));
@@ -523,15 +540,14 @@ static int fetch_err(Ctx& c, int count, double* err) {
   return 0;
 }
 
-// Residual evaluation of Z[cur] in arithmetic `da`, leaving delta where the correction
-// in arithmetic `ca` reads it (BF16 pair, FP32 or FP64), and Err.  With FP16 halves
-// delta is formed in FP32 and, once Err is known, split into FP16 pairs of sigma *
-// delta with sigma = 2^-floor(log2 Err) (|sigma delta_ij| <= 2: delta's entries fall
-// below FP16's normal range as Z converges).
-static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
+// Residual products of Z[cur] in arithmetic `da`, leaving delta where the correction
+// in arithmetic `ca` reads it (BF16 pair, FP32 or FP64) and its norm partials (their
+// count in *blocks).  Every launch reads `gate` (nullptr: none).
+static int delta_products(Ctx& c, Arith da, Arith ca, int cur, const int* gate, int* blocks_out) {
   Workspace& w = *c.w;
   const int np = c.np;
   EpiParams e1 = epi0(np, c.n), e2 = epi0(np, c.n);
+  e1.gate = e2.gate = gate;
   e2.beta = -1.0;
   e2.gamma = 1.0;
   e2.partials = w.partials;
@@ -561,10 +577,10 @@ static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
       HIP_TRY(launch_oz_slice(w.s64, np, s, w.oz_s, w.oz_es, c.st));
       c.oz_s_ready = true;
     }
-    HIP_TRY(launch_oz_slice(w.z64c[cur], np, s, w.oz_z, w.oz_ez, c.st));
+    HIP_TRY(launch_oz_slice(w.z64c[cur], np, s, w.oz_z, w.oz_ez, c.st, gate));
     e1.o64 = w.a64t;
     ZF_TRY(gemm_oz(w.oz_z, w.oz_ez, w.oz_s, w.oz_es, np, s, false, e1, c.st));
-    HIP_TRY(launch_oz_slice(w.a64t, np, s, w.oz_a, w.oz_ea, c.st));
+    HIP_TRY(launch_oz_slice(w.a64t, np, s, w.oz_a, w.oz_ea, c.st, gate));
     e2.o64 = e2.ot64 = w.d64;
     ZF_TRY(gemm_oz(w.oz_z, w.oz_ez, w.oz_a, w.oz_ea, np, s, true, e2, c.st));
     blocks = oz_blocks(np, true);
@@ -574,10 +590,10 @@ static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
       HIP_TRY(launch_crt_residues(w.s64, np, L, c.n, w.cr_s, w.cr_es, c.st));
       c.crt_s_ready = true;
     }
-    HIP_TRY(launch_crt_residues(w.z64c[cur], np, L, c.n, w.cr_z, w.cr_ez, c.st));
+    HIP_TRY(launch_crt_residues(w.z64c[cur], np, L, c.n, w.cr_z, w.cr_ez, c.st, gate));
     e1.o64 = w.a64t;
     ZF_TRY(gemm_crt(w.cr_z, w.cr_ez, w.cr_s, w.cr_es, np, L, c.n, false, w.cr_rho, e1, c.st));
-    HIP_TRY(launch_crt_residues(w.a64t, np, L, c.n, w.cr_a, w.cr_ea, c.st));
+    HIP_TRY(launch_crt_residues(w.a64t, np, L, c.n, w.cr_a, w.cr_ea, c.st, gate));
     e2.o64 = e2.ot64 = w.d64;
     ZF_TRY(gemm_crt(w.cr_z, w.cr_ez, w.cr_a, w.cr_ea, np, L, c.n, true, w.cr_rho, e2, c.st));
     blocks = crt_blocks(np, true);
@@ -594,13 +610,28 @@ static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
     ZF_TRY(gemm_f64(w.z64c[cur], w.a64t, np, true, e2, c.st));
     blocks = f64_blocks(np, np, true);
   }
-  ZF_TRY(fetch_err(c, blocks, err));
-  if (ar_f16(da) && isfinite(*err)) {
-    c.sigma = (*err > 0.0) ? ldexp(1.0, -(int)floor(log2(*err))) : 1.0;
-    HIP_TRY(launch_widen(w.dl32, np, nullptr, nullptr, c.st, nullptr, w.d_hi, w.d_lo, nullptr,
-                         nullptr, (float)c.sigma, PAIR_F16));
-  }
+  *blocks_out = blocks;
   return 0;
+}
+
+// With FP16 halves delta is formed in FP32 and, once Err is known, split into FP16
+// pairs of sigma * delta with sigma = 2^-floor(log2 Err) (|sigma delta_ij| <= 2:
+// delta's entries fall below FP16's normal range as Z converges).
+static int delta_f16_split(Ctx& c, Arith da, double err) {
+  if (!ar_f16(da) || !isfinite(err)) return 0;
+  Workspace& w = *c.w;
+  c.sigma = (err > 0.0) ? ldexp(1.0, -(int)floor(log2(err))) : 1.0;
+  HIP_TRY(launch_widen(w.dl32, c.np, nullptr, nullptr, c.st, nullptr, w.d_hi, w.d_lo, nullptr,
+                       nullptr, (float)c.sigma, PAIR_F16));
+  return 0;
+}
+
+// Residual evaluation of Z[cur] with Err returned to the host (one synchronization).
+static int delta_eval(Ctx& c, Arith da, Arith ca, int cur, double* err) {
+  int blocks = 0;
+  ZF_TRY(delta_products(c, da, ca, cur, nullptr, &blocks));
+  ZF_TRY(fetch_err(c, blocks, err));
+  return delta_f16_split(c, da, *err);
 }
 
 // Q = sum_{k=1..m} c_k delta^k by Horner over symmetric GEMMs (m >= 2) in arithmetic
@@ -612,7 +643,7 @@ struct QRef {
   const double* f64;
 };
 
-static int build_q(Ctx& c, Arith da, Arith ca, QRef* q) {
+static int build_q(Ctx& c, Arith da, Arith ca, QRef* q, const int* gate) {
   Workspace& w = *c.w;
   const int np = c.np, m = c.order;
   const u16 *bh = w.d_hi, *bl = w.d_lo;
@@ -623,6 +654,7 @@ static int build_q(Ctx& c, Arith da, Arith ca, QRef* q) {
   const double sg = f16 ? c.sigma : 1.0;
   for (int k = m - 1; k >= 1; --k) {
     EpiParams e = epi0(np, c.n);
+    e.gate = gate;
     e.alpha = c.c[k] * sg;
     e.beta = ((k == m - 1) ? c.c[m] : 1.0) / sg;
     if (da == AR_F64 || da == AR_EMU || da == AR_CRT) e.d64 = w.d64;
@@ -661,16 +693,18 @@ static int build_q(Ctx& c, Arith da, Arith ca, QRef* q) {
 }
 
 // Z[cur] -> Z[cur ^ 1] = Z + Z Q, Q in arithmetic `ca`; the master Z is FP64 when
-// `high` (refinement phase after an FP64 residual), else FP32.
-static int update(Ctx& c, Arith da, Arith ca, bool high, int cur) {
+// `high` (refinement phase after an FP64 residual), else FP32.  Every launch reads
+// `gate` (nullptr: none).
+static int update(Ctx& c, Arith da, Arith ca, bool high, int cur, const int* gate) {
   Workspace& w = *c.w;
   const int np = c.np, nxt = cur ^ 1;
   QRef q{w.d_hi, w.d_lo, w.dl32, w.d64};
   double beta = 1.0;
   if (c.order == 1) beta = c.c[1];  // Q = c_1 delta: fold the scale into GEMM4
-  else ZF_TRY(build_q(c, da, ca, &q));
+  else ZF_TRY(build_q(c, da, ca, &q, gate));
   if (ar_f16(ca)) beta /= c.sigma;  // the pairs hold sigma * Q
   EpiParams e = epi0(np, c.n);
+  e.gate = gate;
   e.alpha = 1.0;
   e.beta = beta;
   e.pair_fmt = ar_f16(ca) ? PAIR_F16 : PAIR_BF16;
@@ -709,35 +743,74 @@ struct PhaseOut {
   bool capped = false;
 };
 
-// One phase of Algorithm 2: evaluate, stop test, update, ping-pong.
+// One phase of Algorithm 2: evaluate, stop test, update, ping-pong.  The stop test
+// runs on the device (launch_norm_decide) and the host queues one sweep ahead: the
+// update of sweep it and the evaluation of sweep it + 1 are launched before the host
+// reads sweep it's decision, and if that decision was to stop, the gate it set makes
+// every one of those launches return at once (the buffer of the previous iterate is
+// therefore never overwritten).  The GPU thus never waits for the host between
+// sweeps.  With FP16 halves the next products need Err on the host (the scale of
+// delta's split), so that phase reads each decision before it goes on.
 static int run_phase(Ctx& c, Arith da, Arith ca, bool high, int stop_rule, int max_updates,
                      int& cur, std::vector<double>& hist, PhaseOut& out) {
   static const char* kName[8] = {"BF16x3", "BF16", "FP32",          "FP64",
                                  "FP16x3", "FP16", "emulated FP64", "residue-emulated FP64"};
   TraceRange phase_range(high ? "zf.phase_high" : "zf.phase_low");
-  double prev = 0.0;
-  for (int it = 0;; ++it) {
-    double err = 0.0;
-    {
-      TraceRange r("zf.residual_eval");
-      ZF_TRY(delta_eval(c, (high && it == 0 && c.crt_first) ? AR_CRT : da, ca, cur, &err));
+  Workspace& w = *c.w;
+  const bool ahead = !ar_f16(da);
+  const int pw = c.order + 1;
+  auto eval_arith = [&](int it) { return (high && it == 0 && c.crt_first) ? AR_CRT : da; };
+  // residual products of sweep it on buffer b, then its device-side stop test
+  auto enqueue_eval = [&](int it, int b) -> int {
+    TraceRange r("zf.residual_eval");
+    int blocks = 0;
+    ZF_TRY(delta_products(c, eval_arith(it), ca, b, w.gate, &blocks));
+    HIP_TRY(launch_norm_decide(w.partials, blocks, it, stop_rule == ZF_STOP_MONOTONE ? 1 : 0, pw,
+                               w.gate, w.prev_dev, w.box_dev + 2 * (it % kBoxSlots), c.st));
+    return 0;
+  };
+  HIP_TRY(hipMemsetAsync(w.gate, 0, sizeof(int), c.st));
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(ZF_ERR_HIP, "hipEventCreate failed");
+  }
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      (void)hipEventDestroy(e[0]);
+      (void)hipEventDestroy(e[1]);
     }
+  } guard{ev};
+  double prev = 0.0;
+  ZF_TRY(enqueue_eval(0, cur));
+  HIP_TRY(hipEventRecord(ev[0], c.st));
+  for (int it = 0;; ++it) {
+    const bool capped = it >= max_updates;
+    const size_t spec = g_prof.pending.size();  // timed launches queued ahead start here
+    if (ahead && !capped) {  // queued before the decision of sweep it is known
+      TraceRange r("zf.update");
+      ZF_TRY(update(c, da, ca, high, cur, w.gate));
+      ZF_TRY(enqueue_eval(it + 1, cur ^ 1));
+      HIP_TRY(hipEventRecord(ev[(it + 1) & 1], c.st));
+    }
+    HIP_TRY(hipEventSynchronize(ev[it & 1]));
+    const volatile double* box = w.box + 2 * (it % kBoxSlots);
+    const double err = box[0];
+    const int code = (int)box[1];
     out.evals++;
     hist.push_back(err);
-    bool stop = false;
-    if (it > 0 && isfinite(err)) {
-      if (stop_rule == ZF_STOP_MONOTONE) stop = err >= prev;
-      else stop = err > pow(prev, (double)(c.order + 1));
-    }
     if (c.log)
       log_line("\"event\": \"eval\", \"n\": %d, \"arith\": \"%s\", \"phase\": \"%s\", \"it\": %d, "
                "\"err_f\": %.17g, \"rms\": %.6e, \"stop\": %s",
-               c.n, kName[(high && it == 0 && c.crt_first) ? AR_CRT : da], high ? "high" : "low",
-               it, err, err / sqrt((double)c.n),
-               stop ? "true" : "false");
-    if (!isfinite(err))
+               c.n, kName[eval_arith(it)], high ? "high" : "low", it, err, err / sqrt((double)c.n),
+               code == 1 ? "true" : "false");
+    if (code != 0)  // the launches queued ahead were gated off
+      for (size_t k = spec; k < g_prof.pending.size(); ++k) g_prof.pending[k].skip = true;
+    if (code == 2)
       return fail(ZF_ERR_NONFINITE, "residual norm is not finite at %s sweep %d", kName[da], it);
-    if (stop) {
+    if (code == 1) {
       if (err > prev) {  // the previous iterate is still in the other buffer
         cur ^= 1;
         out.updates = it - 1;
@@ -748,15 +821,18 @@ static int run_phase(Ctx& c, Arith da, Arith ca, bool high, int stop_rule, int m
       }
       return 0;
     }
-    if (it >= max_updates) {
+    if (capped) {
       out.updates = it;
       out.err = err;
       out.capped = true;
       return 0;
     }
-    {
+    if (!ahead) {  // FP16 halves: delta's scaled split, then the update and next evaluation
+      ZF_TRY(delta_f16_split(c, eval_arith(it), err));
       TraceRange r("zf.update");
-      ZF_TRY(update(c, da, ca, high, cur));
+      ZF_TRY(update(c, da, ca, high, cur, w.gate));
+      ZF_TRY(enqueue_eval(it + 1, cur ^ 1));
+      HIP_TRY(hipEventRecord(ev[(it + 1) & 1], c.st));
     }
     cur ^= 1;
     prev = err;

@@ -144,6 +144,7 @@ struct EpiParams {
   double* partials;  // per-tile sum of out^2 (FP64), or nullptr
   int pair_fmt;      // PAIR_BF16 / PAIR_F16: format of dhi/dlo and of every pair output
   int kb;            // 16-bit pairs in the K-blocked layout (kb_offset)
+  const int* gate;   // non-null and nonzero: the launch does nothing (a stopped phase)
 };
 
 // Launchers (return hipSuccess or the launch error).  All dimensions must be
@@ -176,7 +177,7 @@ hipError_t launch_gemm_f64(const double* A, int lda, const double* B, int ldb, i
 constexpr int kOzMaxSlices = 8;
 constexpr int kOzMaxOrder = 16384;  // s K 127^2 < 2^31 for every s <= 8
 hipError_t launch_oz_slice(const double* M, int np, int s, signed char* out, int* ex,
-                           hipStream_t st);
+                           hipStream_t st, const int* gate = nullptr);
 hipError_t launch_gemm_oz(const signed char* A, const int* ea, const signed char* B, const int* eb,
                           int np, int s, bool sym, const EpiParams& ep, hipStream_t st);
 int oz_tile_edge(int np, bool sym);
@@ -194,7 +195,7 @@ constexpr int kCrtMaxModuli = 15;
 constexpr int kCrtMaxOrder = 16384;
 int crt_beta(int L, long long K);  // -1 for an unsupported L
 hipError_t launch_crt_residues(const double* M, int np, int L, long long K, signed char* out,
-                               int* ex, hipStream_t st);
+                               int* ex, hipStream_t st, const int* gate = nullptr);
 hipError_t launch_crt_product(const signed char* A, const int* ea, const signed char* B,
                               const int* eb, int np, int L, long long K, bool sym,
                               unsigned char* rho, const EpiParams& ep, hipStream_t st);
@@ -225,6 +226,14 @@ hipError_t launch_unpad_f32(const float* src, int np, int n, double* dst, hipStr
 // out[0] = sqrt(sum of the partials) / div (div = 1: the Frobenius norm itself)
 hipError_t launch_norm_finalize(const double* partials, int count, double* out, hipStream_t st,
                                 double div = 1.0);
+// The stop test of one sweep on the device: Err from the partials, then the rule of
+// Algorithm 2 against the previous Err (state[0]): rule 1 (monotone) stops when Err >=
+// prev, rule 0 (ratio) when Err > prev^pw.  box[0] = Err, box[1] = 0 (go on), 1 (stop)
+// or 2 (Err not finite); a stop or a non-finite Err sets *gate, which every later
+// launch of the phase reads and then does nothing, this one included.  box may be
+// host memory (mapped, coherent).
+hipError_t launch_norm_decide(const double* partials, int count, int it, int rule, int pw,
+                              int* gate, double* state, double* box, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
 // Tracing (zf_api.hip).
