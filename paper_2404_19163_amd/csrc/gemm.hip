@@ -103,9 +103,12 @@ static int grid_blocks(int M, int N, int t, bool sym) {
   return sym ? tm * (tm + 1) / 2 : tm * tn;
 }
 
-// Tile edge of a launch: the largest of 256 / 128 / 64 that divides both output
-// dimensions and still yields at least 128 workgroups (half of the 256 CUs; fewer,
-// larger tiles beat more, smaller ones down to that point).  ZF_X3_TILE /
+// Tile edge of a launch: 256 when it divides both output dimensions and yields at
+// least 128 workgroups (half of the 256 CUs: fewer, larger tiles beat more, smaller
+// ones down to that point), else 128 when that yields at least 192 workgroups (the
+// 128-wide tile runs one 8-wave block per CU), else 64.  Measured on the mixed solve:
+// 64-wide tiles beat 128-wide grids of 136-171 tiles (N = 1536, 2048, 2304) by 3-6%,
+// 128-wide ones win from about 200 tiles on (N = 2560, 2816).  ZF_X3_TILE /
 // ZF_X3_SYM_TILE (64, 128 or 256) force the BF16x3 edge when it divides (tuning).
 int x3_tile_edge(int M, int N, bool sym) {
   const char* env = getenv(sym ? "ZF_X3_SYM_TILE" : "ZF_X3_TILE");
@@ -114,7 +117,7 @@ int x3_tile_edge(int M, int N, bool sym) {
     if ((want == 64 || want == 128 || want == 256) && M % want == 0 && N % want == 0) return want;
   }
   if (M % 256 == 0 && N % 256 == 0 && grid_blocks(M, N, 256, sym) >= 128) return 256;
-  if (grid_blocks(M, N, 128, sym) >= 128) return 128;
+  if (M % 128 == 0 && N % 128 == 0 && grid_blocks(M, N, 128, sym) >= 192) return 128;
   return 64;
 }
 
