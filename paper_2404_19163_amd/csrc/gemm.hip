@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(WM* WN * 64)
 template <int BM, int BN, int BK, int WM, int WN, bool SYM>
 __global__ void __launch_bounds__(WM* WN * 64, 2)
     gemm_f64_kernel(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
-                    int K, int tiles_n, int gm, EpiParams ep, int split_from) {
+                    int K, int tiles_n, int gm, EpiParams ep) {
   using C = F64Cfg<BM, BN, BK, WM, WN>;
   __shared__ double lds[2 * C::STAGE];
   __shared__ double red[C::NT / 64];
@@ -85,122 +85,14 @@ __global__ void __launch_bounds__(WM* WN * 64, 2)
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   int ti, tj;
   tile_coords(bid, tiles_n, SYM, ti, tj, gm);
-  const int pidx = tile_index(ti, tj, tiles_n, SYM);
-  if (pidx >= split_from) return;  // one of the tail kernel's tiles
   const int mode = SYM ? (ti == tj ? 2 : 1) : 0;
-  f64_tile<BM, BN, BK, WM, WN>(A, lda, B, ldb, K, ti * BM, tj * BN, mode, ep, pidx, lds, red);
-}
-
-// The last tiles of an FP64 grid whose last round of blocks would run nearly alone
-// (N = 4096 symmetric: 2080 tiles of 64 on 1024 four-per-CU block slots, 32 tiles
-// left for a third round), launched right after the main grid as `pieces` K ranges
-// per tile, one block each: the last round then holds 4 x 32 short blocks instead of
-// 32 long ones.  The split tiles are those with norm-partial index split_from and
-// above (the main grid skips them), the same tiles whatever order the main grid walks
-// in, so results do not depend on the band height.  Block u takes piece u % pieces of
-// tile split_from + u / pieces.  The block
-// with a tile's last K range adds the other pieces' FP64 partial sums (part, one
-// tile-sized slot per block, added in piece order) and runs the epilogue; it waits
-// only on the tile's earlier pieces, blocks with smaller index that wait on nothing,
-// and the wait is bounded (a block that gives up writes NaN for its tile, which the
-// stop test reports).  flags[u / pieces] counts the finished pieces and is brought
-// back to 0 by the last one.  A kernel of its own: the split's extra registers would
-// cost the main grid a quarter of its block slots.
-constexpr int kF64SpinLimit = 1 << 20;
-
-template <int BM, int BN, int BK, int WM, int WN, bool SYM>
-__global__ void __launch_bounds__(WM* WN * 64, 2)
-    gemm_f64_tail_kernel(const double* __restrict__ A, int lda, const double* __restrict__ B,
-                         int ldb, int K, int tiles_n, EpiParams ep, int split_from, int pieces,
-                         double* __restrict__ part, int* __restrict__ flags) {
-  using C = F64Cfg<BM, BN, BK, WM, WN>;
-  __shared__ double lds[2 * C::STAGE];
-  __shared__ double red[C::NT / 64];
-  __shared__ int ok_s;
-  if (ep.gate && *ep.gate) return;
-  const int u = blockIdx.x, tt = u / pieces, pc = u % pieces;
-  int ti, tj;
-  tile_of_index(split_from + tt, tiles_n, SYM, ti, tj);
-  const int mode = SYM ? (ti == tj ? 2 : 1) : 0;
-  const int kp = K / pieces;
-  F64Acc<BM, BN, BK, WM, WN> acc;
-  f64_mainloop<BM, BN, BK, WM, WN>(A, lda, B, ldb, pc * kp, (pc + 1) * kp, ti * BM, tj * BN, lds,
-                                   acc);
-  // the accumulators as lane-contiguous 16-byte vectors: pair (a, b, h) of thread tid
-  // at ((a FN + b) 2 + h) NT + tid
-  constexpr int SLOT = BM * BN;
-  if (pc < pieces - 1) {
-    double2* dst = reinterpret_cast<double2*>(part + (size_t)u * SLOT);
-#pragma unroll
-    for (int a = 0; a < C::FM; ++a)
-#pragma unroll
-      for (int b = 0; b < C::FN; ++b)
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-          dst[((a * C::FN + b) * 2 + h) * C::NT + threadIdx.x] =
-              make_double2(acc[a][b][2 * h], acc[a][b][2 * h + 1]);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0)
-      __hip_atomic_fetch_add(flags + tt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return;
-  }
-  if (threadIdx.x == 0) {
-    int ok = 1, polls = 0;
-    while (__hip_atomic_load(flags + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < pieces - 1) {
-      if (++polls > kF64SpinLimit) {
-        ok = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-    __hip_atomic_fetch_add(flags + tt, -(pieces - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    ok_s = ok;
-  }
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  // the last piece's own sum, then the earlier pieces in order
-  for (int q = 0; q < pieces - 1; ++q) {
-    const double2* src = reinterpret_cast<const double2*>(part + (size_t)(u - pc + q) * SLOT);
-#pragma unroll
-    for (int a = 0; a < C::FM; ++a)
-#pragma unroll
-      for (int b = 0; b < C::FN; ++b)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const double2 v = src[((a * C::FN + b) * 2 + h) * C::NT + threadIdx.x];
-          acc[a][b][2 * h] += v.x;
-          acc[a][b][2 * h + 1] += v.y;
-        }
-  }
-  if (!ok_s) {
-#pragma unroll
-    for (int a = 0; a < C::FM; ++a)
-#pragma unroll
-      for (int b = 0; b < C::FN; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[a][b][r] = __builtin_nan("");
-  }
-  f64_epilogue<BM, BN, BK, WM, WN>(acc, ti * BM, tj * BN, mode, ep,
-                                   tile_index(ti, tj, tiles_n, SYM), red);
+  f64_tile<BM, BN, BK, WM, WN>(A, lda, B, ldb, K, ti * BM, tj * BN, mode, ep,
+                               tile_index(ti, tj, tiles_n, SYM), lds, red);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// CUs of the current device (cached per device), 0 if unknown.
-static int device_cus() {
-  static int cached[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (!cached[dev]) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    cached[dev] = v;
-  }
-  return cached[dev];
-}
-
 static bool dims_ok(int M, int N, int K, bool sym) {
   return M > 0 && N > 0 && K > 0 && M % kTile == 0 && N % kTile == 0 && K % kTile == 0 &&
          (!sym || M == N);
@@ -290,60 +182,16 @@ static void f32_launch(const float* A, int lda, const float* B, int ldb, int M, 
                        0, st, A, lda, B, ldb, K, N / BN, tile_group(M, BM), ep);
 }
 
-// The FP64 tail split (gemm_f64_kernel) of a grid of T tiles of 64 with contracted
-// dimension K: in a grid of at least one full round of the 4-per-CU block slots, the
-// tiles left for a last round that is at most a quarter full, as 4 K pieces each
-// (main = T - tail blocks first).  Grids smaller than one round keep one block per
-// tile.  ZF_F64_TAIL = 0 turns the split off (tuning, tests).
-static void f64_tail_plan(int T, int K, int& main_blocks, int& pieces) {
-  main_blocks = T;
-  pieces = 1;
-  const char* env = getenv("ZF_F64_TAIL");
-  if (env && atoi(env) == 0) return;
-  const int slots = 4 * device_cus();
-  if (slots <= 0 || T < slots || K % (4 * 16)) return;
-  const int tail = T % slots;
-  if (tail == 0 || 4 * tail > slots) return;
-  main_blocks = T - tail;
-  pieces = 4;
-}
-
-size_t f64_split_part_elems() { return (size_t)device_cus() * 4 * 64 * 64; }
-int f64_split_flag_count() { return device_cus(); }
-
 template <int BM, int BN, int WM, int WN>
 static void f64_launch(const double* A, int lda, const double* B, int ldb, int M, int N, int K,
-                       bool sym, int blocks, const EpiParams& ep, hipStream_t st,
-                       const F64Split* sp) {
-  int main_blocks = blocks, pieces = 1;
-  if (BM == 64 && sp && sp->part && sp->flags) {
-    f64_tail_plan(blocks, K, main_blocks, pieces);
-    const int tail = blocks - main_blocks;
-    if (pieces > 1 && ((size_t)tail * pieces * BM * BN > sp->part_elems || tail > sp->flag_count)) {
-      main_blocks = blocks;
-      pieces = 1;
-    }
-  }
-  // the main grid walks every tile and leaves tiles main_blocks.. (by norm-partial
-  // index) to the tail kernel
+                       bool sym, int blocks, const EpiParams& ep, hipStream_t st) {
   if (sym)
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, 16, WM, WN, true>), dim3(blocks),
-                       dim3(WM * WN * 64), 0, st, A, lda, B, ldb, K, N / BN, sym_group(), ep,
-                       main_blocks);
+                       dim3(WM * WN * 64), 0, st, A, lda, B, ldb, K, N / BN, sym_group(), ep);
   else
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, 16, WM, WN, false>), dim3(blocks),
                        dim3(WM * WN * 64), 0, st, A, lda, B, ldb, K, N / BN, tile_group(M, BM),
-                       ep, main_blocks);
-  if (main_blocks == blocks) return;
-  const int grid = (blocks - main_blocks) * pieces;
-  if (sym)
-    hipLaunchKernelGGL((gemm_f64_tail_kernel<BM, BN, 16, WM, WN, true>), dim3(grid),
-                       dim3(WM * WN * 64), 0, st, A, lda, B, ldb, K, N / BN, ep, main_blocks,
-                       pieces, sp->part, sp->flags);
-  else
-    hipLaunchKernelGGL((gemm_f64_tail_kernel<BM, BN, 16, WM, WN, false>), dim3(grid),
-                       dim3(WM * WN * 64), 0, st, A, lda, B, ldb, K, N / BN, ep, main_blocks,
-                       pieces, sp->part, sp->flags);
+                       ep);
 }
 
 template <int PM>
@@ -407,13 +255,13 @@ hipError_t launch_gemm_f32(const float* A, int lda, const float* B, int ldb, int
 }
 
 hipError_t launch_gemm_f64(const double* A, int lda, const double* B, int ldb, int M, int N, int K,
-                           bool sym, const EpiParams& ep, hipStream_t st, const F64Split* sp) {
+                           bool sym, const EpiParams& ep, hipStream_t st) {
   if (!dims_ok(M, N, K, sym)) return hipErrorInvalidValue;
   const int blocks = f64_blocks(M, N, sym);
   if (f64_tile_edge(M, N, sym) == 128)
-    f64_launch<128, 128, 2, 2>(A, lda, B, ldb, M, N, K, sym, blocks, ep, st, nullptr);
+    f64_launch<128, 128, 2, 2>(A, lda, B, ldb, M, N, K, sym, blocks, ep, st);
   else
-    f64_launch<64, 64, 2, 2>(A, lda, B, ldb, M, N, K, sym, blocks, ep, st, sp);
+    f64_launch<64, 64, 2, 2>(A, lda, B, ldb, M, N, K, sym, blocks, ep, st);
   return hipGetLastError();
 }
 

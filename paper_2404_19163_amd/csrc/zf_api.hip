@@ -208,8 +208,6 @@ struct Workspace {
   int* gate = nullptr;
   double* prev_dev = nullptr;
   double *box = nullptr, *box_dev = nullptr;
-  // partial sums and flags of the FP64 GEMMs' tail split
-  F64Split f64sp = {};
 };
 constexpr int kBoxSlots = 8;
 
@@ -307,13 +305,6 @@ static int ws_build(Workspace& w, int dev, int np, bool x3, bool f64, bool f32, 
     for (int b = 0; b < 2; ++b) ZF_TRY(ws_alloc(w, &w.zc32[b], m));
   }
   if (f64) {
-    w.f64sp.part_elems = f64_split_part_elems();
-    w.f64sp.flag_count = f64_split_flag_count();
-    if (w.f64sp.part_elems > 0 && w.f64sp.flag_count > 0) {
-      ZF_TRY(ws_alloc(w, &w.f64sp.part, w.f64sp.part_elems));
-      ZF_TRY(ws_alloc(w, &w.f64sp.flags, (size_t)w.f64sp.flag_count));
-      HIP_TRY(hipMemset(w.f64sp.flags, 0, (size_t)w.f64sp.flag_count * sizeof(int)));
-    }
     ZF_TRY(ws_alloc(w, &w.s64, m));
     ZF_TRY(ws_alloc(w, &w.a64t, m));
     ZF_TRY(ws_alloc(w, &w.d64, m));
@@ -448,8 +439,7 @@ static int gemm_f64(const double* A, const double* B, int np, bool sym, const Ep
     pe.flops = 2.0 * (double)f64_blocks(np, np, sym) * t * t * (double)np;
     HIP_TRY(hipEventRecord(pe.a, st));
   }
-  HIP_TRY(launch_gemm_f64(A, np, B, np, np, np, np, sym, ep, st,
-                          g_ws.f64sp.part ? &g_ws.f64sp : nullptr));
+  HIP_TRY(launch_gemm_f64(A, np, B, np, np, np, np, sym, ep, st));
   if (prof) {
     HIP_TRY(hipEventRecord(pe.b, st));
     g_prof.pending.push_back(pe);
@@ -1529,20 +1519,7 @@ static int t_gemm_impl(int precision, int oz_slices, int sym, int m, int nn, int
         he = launch_gemm_x3(ah, al, np, bh, bl, np, np, np, np, sym != 0, ep, st, pm);
     }
   } else if (he == hipSuccess) {
-    // the tail-split buffers the solver's FP64 launches use
-    F64Split sp = {};
-    sp.part_elems = f64_split_part_elems();
-    sp.flag_count = f64_split_flag_count();
-    if (sp.part_elems > 0 && sp.flag_count > 0) {
-      if ((rc = alloc(sp.part_elems * 8, (void**)&sp.part)) ||
-          (rc = alloc((size_t)sp.flag_count * 4, (void**)&sp.flags))) {
-        cleanup();
-        return rc;
-      }
-      he = hipMemsetAsync(sp.flags, 0, (size_t)sp.flag_count * 4, st);
-    }
-    if (he == hipSuccess)
-      he = launch_gemm_f64(a64, np, b64, np, np, np, np, sym != 0, ep, st, sp.part ? &sp : nullptr);
+    he = launch_gemm_f64(a64, np, b64, np, np, np, np, sym != 0, ep, st);
   }
   double* nrm = nullptr;
   if (he == hipSuccess && norm_sq) {

@@ -71,18 +71,6 @@ __host__ __device__ inline int tile_index(int ti, int tj, int tiles_n, bool sym)
   return sym ? ti * tiles_n - ti * (ti - 1) / 2 + (tj - ti) : ti * tiles_n + tj;
 }
 
-// The tile whose norm-partial index is idx (the inverse of tile_index).
-__host__ __device__ inline void tile_of_index(int idx, int tiles_n, bool sym, int& ti, int& tj) {
-  if (!sym) {
-    ti = idx / tiles_n;
-    tj = idx - ti * tiles_n;
-    return;
-  }
-  ti = 0;
-  while (idx >= tiles_n - ti) idx -= tiles_n - ti++;
-  tj = ti + idx;
-}
-
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).
 // Renumber so that each XCD receives a contiguous run of tiles, which then share
 // operand rows in that XCD's L2.  A permutation of [0, nblocks) when nblocks is a

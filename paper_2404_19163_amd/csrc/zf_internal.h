@@ -166,21 +166,8 @@ int f32_tile_edge(int M, int N, bool sym);
 int f32_blocks(int M, int N, bool sym);
 hipError_t launch_gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int N, int K,
                            bool sym, const EpiParams& ep, hipStream_t st);
-// sp: buffers of the FP64 tail split (gemm.hip), or nullptr for one block per tile.
-// With at least f64_split_part_elems() doubles and f64_split_flag_count() flags (zero
-// before the first launch; every launch leaves them zero), a grid whose last round of
-// 4-per-CU block slots is at most a quarter full runs those tiles as 4 K pieces each.
-struct F64Split {
-  double* part;
-  int* flags;
-  size_t part_elems;
-  int flag_count;
-};
-size_t f64_split_part_elems();
-int f64_split_flag_count();
 hipError_t launch_gemm_f64(const double* A, int lda, const double* B, int ldb, int M, int N, int K,
-                           bool sym, const EpiParams& ep, hipStream_t st,
-                           const F64Split* sp = nullptr);
+                           bool sym, const EpiParams& ep, hipStream_t st);
 
 // FP64 products emulated with 7-bit integer slices on the int8 matrix cores
 // (ozaki.hip).  Slices of M (np x np FP64, row-major): s planes of np x np signed

@@ -36,9 +36,6 @@ static void full_grid(int T, int gm) {
     CHECK(ti >= 0 && ti < T && tj >= 0 && tj < T, "full T=%d gm=%d bid %d -> (%d,%d)", T, gm, b, ti, tj);
     const int idx = tile_index(ti, tj, T, false);
     CHECK(idx == ti * T + tj, "full index");
-    int ri = -1, rj = -1;
-    tile_of_index(idx, T, false, ri, rj);
-    CHECK(ri == ti && rj == tj, "tile_of_index(%d) full", idx);
     CHECK(seen[idx]++ == 0, "full T=%d gm=%d tile (%d,%d) twice", T, gm, ti, tj);
   }
 }
@@ -54,9 +51,6 @@ static void sym_grid(int T, int gm) {
     CHECK(ti >= 0 && ti <= tj && tj < T, "sym T=%d gm=%d bid %d -> (%d,%d)", T, gm, b, ti, tj);
     const int idx = tile_index(ti, tj, T, true);
     CHECK(idx >= 0 && idx < cnt, "sym index %d out of range", idx);
-    int ri = -1, rj = -1;
-    tile_of_index(idx, T, true, ri, rj);
-    CHECK(ri == ti && rj == tj, "tile_of_index(%d) = (%d,%d), not (%d,%d)", idx, ri, rj, ti, tj);
     CHECK(seen[idx]++ == 0, "sym T=%d gm=%d tile (%d,%d) twice", T, gm, ti, tj);
   }
   // the row-major triangle index itself: row ti starts after the rows above it

@@ -313,45 +313,6 @@ def test_gemm_symmetric_delta_n4096(zf, k):
     assert nsq == pytest.approx(math.fsum((C * C).ravel().tolist()), rel=1e-12)
 
 
-@pytest.mark.parametrize("n,k,sym", [(4096, 4096, True), (3000, 2500, True), (5120, 1500, False)])
-def test_gemm_f64_tail_split(zf, n, k, sym, monkeypatch):
-    """FP64 grids whose last round of four-per-CU block slots is at most a quarter full
-    run their last tiles as 4 K pieces each, finished by the last piece with the others'
-    partial sums (N = 4096 symmetric: 2080 tiles, the last 32 split; padded 3072
-    symmetric: 1176 tiles, 152 split; 5120 full: 6400 tiles, 256 split).  Checked
-    against the FP64 product within the dot-product bound, against the one-block-per-
-    tile grid (ZF_F64_TAIL=0; equal up to the rounding of the split sums, not bit for
-    bit: the split ran), for exact mirroring and the norm, and twice in a row bit for
-    bit (the flags come back to zero)."""
-    rng = np.random.default_rng(n + k + sym)
-    A = rng.standard_normal((n, k)) / math.sqrt(k)
-    if sym:
-        M = rng.standard_normal((k, k))
-        B = A @ ((M + M.T) / 2)
-    else:
-        B = rng.standard_normal((n, k))
-    D = rng.standard_normal((n, n))
-    if sym:
-        D = D + D.T
-    args = dict(sym=sym, alpha=0.5, D=_cuda(D), beta=-1.0, gamma=1.0)
-    monkeypatch.setenv("ZF_F64_TAIL", "0")
-    C_tile, _ = zf.t_gemm("fp64", _cuda(A), _cuda(B), **args)
-    monkeypatch.delenv("ZF_F64_TAIL")
-    C, nsq = zf.t_gemm("fp64", _cuda(A), _cuda(B), **args)
-    C2, nsq2 = zf.t_gemm("fp64", _cuda(A), _cuda(B), **args)
-    assert torch.equal(C, C2) and nsq == nsq2
-    assert not torch.equal(C, C_tile)
-    C, C_tile = C.cpu().numpy(), C_tile.cpu().numpy()
-    ref = 0.5 * D - A @ B.T + np.eye(n)
-    tol = 2 * k * U64 * (np.abs(A) @ np.abs(B).T) + 2 * U64 * (np.abs(ref) + 1.0)
-    sel = np.triu(np.ones((n, n), dtype=bool)) if sym else np.ones((n, n), dtype=bool)
-    if sym:
-        assert np.array_equal(C, C.T)
-    assert np.all((np.abs(C - ref) <= tol)[sel])
-    assert np.all((np.abs(C - C_tile) <= 2 * tol)[sel])
-    assert nsq == pytest.approx(math.fsum((C * C).ravel().tolist()), rel=1e-12)
-
-
 @pytest.mark.parametrize("tile", ["64", "128", "256"])
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16", "fp16x3"])
 @pytest.mark.parametrize("sym", [False, True])
