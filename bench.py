@@ -637,7 +637,9 @@ def bench_md(args) -> dict:
     random-walking by N(0, 0.01 A) per coordinate; each frame refined from (a) the
     previous frame's Z, (b) the learned guess, (c) the scaled identity.  The network
     is trained on the first 16 frames (labels from their refined Z) and evaluated on
-    the rest; reported per strategy: mean updates and ms per frame."""
+    the rest; reported per strategy: mean updates and ms per frame.  Every frame's
+    refinement phase takes the bench's --refine (default: first residual from
+    residues, final residual in FP64), as the single-matrix legs do."""
     import numpy as np
     import torch
 
@@ -655,17 +657,18 @@ def bench_md(args) -> dict:
     losses, _ = guess.train(X, Y, steps=300, lr=3e-3, seed=args.seed)
     stats = {"warm": [], "learned": [], "identity": []}
     Z = torch.empty_like(S[0])
-    prev = zf.refine(S[ntrain - 1], None).Z.clone()
+    rf = args.refine
+    prev = zf.refine(S[ntrain - 1], None, refine=rf).Z.clone()
     for f in range(ntrain, frames):
         for kind in ("warm", "learned", "identity"):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             if kind == "warm":
-                r = zf.refine(S[f], prev, out=Z)
+                r = zf.refine(S[f], prev, out=Z, refine=rf)
             elif kind == "learned":
-                r = zf.refine(S[f], None, out=Z, guess="learned")
+                r = zf.refine(S[f], None, out=Z, guess="learned", refine=rf)
             else:
-                r = zf.refine(S[f], None, out=Z)
+                r = zf.refine(S[f], None, out=Z, refine=rf)
             torch.cuda.synchronize()
             stats[kind].append((time.perf_counter() - t1, r.iters, r.low_evals, r.high_evals,
                                 r.final_rms, getattr(r, "z0_used", -1)))
@@ -688,7 +691,8 @@ def bench_md(args) -> dict:
         "config": {"workload": f"{frames} frames of the N=3000 Gaussian-kernel system (sigma 1.0 A), "
                                "positions random-walking by N(0, 0.01 A) per coordinate",
                    "network": f"trained on frames 0..{ntrain - 1} ({len(losses)} Adam steps, "
-                              f"loss {losses[0]:.3g} -> {losses[-1]:.3g})"},
+                              f"loss {losses[0]:.3g} -> {losses[-1]:.3g})",
+                   "refine": REFINE_DESC[rf]},
         "strategies": summary,
     }
     return line
