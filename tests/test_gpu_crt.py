@@ -170,3 +170,26 @@ def test_fullsize_crt(zf, wl):
         assert r.status == 0 and rms <= 1e-6
         assert rms <= 2.0 * O.residual_rms(S, Zd) + 1e-12
         assert np.linalg.norm(Z - Zd) / np.linalg.norm(Zd) <= 1e-6
+
+
+def test_warm_start_crt_first(zf):
+    """An MD-like warm start at N = 3000 (two frames of the random-walk trajectory; the
+    second refined from the first's Z) with the residue-emulated first refinement
+    residual: the FP64 final residual meets the FP64 bar by the oracle, and Z, the
+    update count and the evaluation counts match the FP64-residual refinement's."""
+    f0, f1 = list(inputs.md_trajectory(3000, 2, 0))
+    S0, S1 = _cuda(f0), _cuda(f1)
+    prev = zf.refine(S0, None, precision="bf16x3", refine="crt_first").Z.clone()
+    runs = {}
+    for mode in ("crt_first", "f64_delta"):
+        r = zf.refine(S1, prev, precision="bf16x3", refine=mode)
+        Z = r.Z.cpu().numpy()
+        rms = O.residual_rms(f1, Z)
+        print(f"warm {mode}: {r.iters} updates, {r.low_evals}+{r.high_evals} evals, final "
+              f"{r.final_rms:.3e}, oracle {rms:.3e}", flush=True)
+        assert r.status == 0 and r.z0_used == zf.Z0_GIVEN
+        assert rms <= 1e-10 and r.final_rms == pytest.approx(rms, rel=1e-6)
+        runs[mode] = (r, Z)
+    (rc, Zc), (rd, Zd) = runs["crt_first"], runs["f64_delta"]
+    assert (rc.iters, rc.low_evals, rc.high_evals) == (rd.iters, rd.low_evals, rd.high_evals)
+    assert np.linalg.norm(Zc - Zd) / np.linalg.norm(Zd) <= 1e-9
